@@ -1,0 +1,243 @@
+"""CPU oracle for the Heston / Milstein Monte-Carlo path -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The product library never calls it and shares no code with it.
+
+Contents
+--------
+- ``heston_oracle.c`` (built to ``liboracle.so`` with gcc): Philox4x32-10, the
+  Box-Muller normals, one Milstein path at a time in FP64 with its payoff and
+  pathwise estimators, and forward-mode derivatives of the payoff.
+- this module: ctypes marshalling, plus the estimators built on top of the
+  per-path records -- means and standard errors (two-pass), central
+  bump-and-revalue Greeks on common random numbers by full re-simulation of
+  every bumped scenario, and quasi-Monte-Carlo replicate estimates.
+- ``analytic``: Heston characteristic-function prices and Greeks, Black-Scholes.
+- ``sobol``: Sobol points (Gray-code order, digital shifts) and the Brownian
+  bridge, giving quasi-random normals for the same path simulator.
+- ``bk``: Broadie-Kaya exact simulation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, astuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "heston_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT = 0, 1, 2, 3
+FULL_TRUNC, ABSORB = 0, 1
+REC_FIELDS = ("S_T", "V_T", "Sbar", "pay", "pw_delta", "pw_rho")
+TAN_FIELDS = ("pay", "d_S0", "d_v0", "d_r", "d_kappa", "d_theta", "d_sigma", "d_rho")
+PARAM_NAMES = ("S0", "K", "r", "T", "v0", "kappa", "theta", "sigma", "rho")
+
+
+@dataclass(frozen=True)
+class Params:
+    S0: float
+    K: float
+    r: float
+    T: float
+    v0: float
+    kappa: float
+    theta: float
+    sigma: float
+    rho: float
+
+    def replace(self, **kw) -> "Params":
+        d = dict(zip(PARAM_NAMES, astuple(self)))
+        d.update(kw)
+        return Params(**d)
+
+
+class _CParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in PARAM_NAMES]
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared",
+                               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        u32p, dp = P(ctypes.c_uint32), P(ctypes.c_double)
+        sig = [P(_CParams), ctypes.c_int, ctypes.c_uint32, u32p, ctypes.c_uint32, ctypes.c_int,
+               ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, dp, dp, ctypes.c_int, dp]
+        for name in ("or_simulate", "or_tangent"):
+            f = getattr(L, name)
+            f.argtypes = sig
+            f.restype = ctypes.c_int
+        L.or_philox_block.argtypes = [u32p, u32p, ctypes.c_uint64, u32p]
+        L.or_philox_block.restype = None
+        L.or_normals_block.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                       ctypes.c_uint32, dp, dp]
+        L.or_normals_block.restype = None
+        L.or_uniform.argtypes = [ctypes.c_uint32]
+        L.or_uniform.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
+
+
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 words for arrays ctr [n,4] and key [n,2] (uint32)."""
+    ctr = np.ascontiguousarray(np.atleast_2d(ctr), dtype=np.uint32)
+    key = np.ascontiguousarray(np.atleast_2d(key), dtype=np.uint32)
+    n = ctr.shape[0]
+    out = np.empty((n, 4), dtype=np.uint32)
+    lib().or_philox_block(_ptr(ctr, ctypes.c_uint32), _ptr(key, ctypes.c_uint32), n,
+                          _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def normals(seed: int, first: int, n_paths: int, n_steps: int):
+    """The Philox/Box-Muller normals (Za, Zb), each [n_paths, n_steps]."""
+    za = np.empty((n_paths, n_steps))
+    zb = np.empty((n_paths, n_steps))
+    lib().or_normals_block(seed, first, n_paths, n_steps, _ptr(za, ctypes.c_double),
+                           _ptr(zb, ctypes.c_double))
+    return za, zb
+
+
+def _fix_array(fixings):
+    if fixings is None:
+        return None, 0
+    f = np.ascontiguousarray(fixings, dtype=np.uint32)
+    return f, int(f.size)
+
+
+def simulate(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int = 0,
+             n_paths: int = 1, mode: int = FULL_TRUNC, fixings=None, za=None, zb=None,
+             threads: int = 1) -> np.ndarray:
+    """Per-path records [n_paths, 6] = (S_T, V_T, Sbar, pay, pw_delta, pw_rho)."""
+    return _run("or_simulate", len(REC_FIELDS), p, opt_type, n_steps, seed, first, n_paths, mode,
+                fixings, za, zb, threads)
+
+
+def tangent(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int = 0,
+            n_paths: int = 1, mode: int = FULL_TRUNC, fixings=None, za=None, zb=None,
+            threads: int = 1) -> np.ndarray:
+    """Per-path [n_paths, 8] = (pay, d/dS0, d/dv0, d/dr, d/dkappa, d/dtheta, d/dsigma, d/drho)."""
+    return _run("or_tangent", len(TAN_FIELDS), p, opt_type, n_steps, seed, first, n_paths, mode,
+                fixings, za, zb, threads)
+
+
+def _run(fn, width, p, opt_type, n_steps, seed, first, n_paths, mode, fixings, za, zb, threads):
+    fix, nf = _fix_array(fixings)
+    if za is not None:
+        za = np.ascontiguousarray(za, dtype=np.float64)
+        zb = np.ascontiguousarray(zb, dtype=np.float64)
+        assert za.shape == (n_paths, n_steps) and zb.shape == za.shape
+    out = np.empty((n_paths, width))
+    cp = _CParams(*astuple(p))
+    rc = getattr(lib(), fn)(ctypes.byref(cp), opt_type, n_steps, _ptr(fix, ctypes.c_uint32), nf,
+                            mode, seed & (2**64 - 1), first, n_paths, _ptr(za, ctypes.c_double),
+                            _ptr(zb, ctypes.c_double), threads, _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError(f"{fn}: invalid argument")
+    return out
+
+
+# --------------------------------------------------------------------------
+# Estimators on top of the per-path records.
+
+def mean_se(y: np.ndarray):
+    """Sample mean and its standard error, two-pass: sqrt(sum (y-mean)^2 / (n(n-1)))."""
+    y = np.asarray(y, dtype=np.float64)
+    n = y.shape[0]
+    m = y.sum(axis=0) / n
+    ss = ((y - m) ** 2).sum(axis=0)
+    return m, np.sqrt(ss / (n * (n - 1)))
+
+
+@dataclass(frozen=True)
+class Bumps:
+    """Central bump sizes: relative for S0 and v0, absolute for r and T."""
+    S0_rel: float = 0.01
+    v0_rel: float = 0.01
+    r_abs: float = 1e-4
+    T_abs: float = 1.0 / 365.0
+
+
+SCENARIOS = ("base", "S0+", "S0-", "v0+", "v0-", "r+", "r-", "T+", "T-")
+
+
+def scenario_params(p: Params, b: Bumps):
+    hS, hv = b.S0_rel * p.S0, b.v0_rel * p.v0
+    return {
+        "base": p,
+        "S0+": p.replace(S0=p.S0 + hS), "S0-": p.replace(S0=p.S0 - hS),
+        "v0+": p.replace(v0=p.v0 + hv), "v0-": p.replace(v0=p.v0 - hv),
+        "r+": p.replace(r=p.r + b.r_abs), "r-": p.replace(r=p.r - b.r_abs),
+        "T+": p.replace(T=p.T + b.T_abs), "T-": p.replace(T=p.T - b.T_abs),
+    }
+
+
+def scenario_payoffs(p: Params, opt_type: int, n_steps: int, seed: int, n_paths: int,
+                     first: int = 0, mode: int = FULL_TRUNC, fixings=None, bumps: Bumps = Bumps(),
+                     za=None, zb=None, threads: int = 1):
+    """Per-path discounted payoffs of all 9 scenarios on common random numbers.
+
+    Every scenario is a complete re-simulation with the bumped parameter; the
+    step count N and the fixing step indices stay fixed, so a T bump rescales
+    dt and the fixing times."""
+    out = {}
+    base_rec = None
+    for name, q in scenario_params(p, bumps).items():
+        rec = simulate(q, opt_type, n_steps, seed, first, n_paths, mode, fixings, za, zb, threads)
+        out[name] = rec[:, 3]
+        if name == "base":
+            base_rec = rec
+    return out, base_rec
+
+
+def greek_samples(pay: dict, p: Params, bumps: Bumps = Bumps()):
+    """Per-path central-difference Greek samples (their means are the Greeks)."""
+    hS, hv = bumps.S0_rel * p.S0, bumps.v0_rel * p.v0
+    return {
+        "price": pay["base"],
+        "delta": (pay["S0+"] - pay["S0-"]) / (2 * hS),
+        "gamma": (pay["S0+"] - 2 * pay["base"] + pay["S0-"]) / (hS * hS),
+        "vega": (pay["v0+"] - pay["v0-"]) / (2 * hv),
+        "rho": (pay["r+"] - pay["r-"]) / (2 * bumps.r_abs),
+        "theta": -(pay["T+"] - pay["T-"]) / (2 * bumps.T_abs),
+    }
+
+
+def price_greeks(p: Params, opt_type: int, n_paths: int, n_steps: int, seed: int,
+                 mode: int = FULL_TRUNC, fixings=None, bumps: Bumps | None = Bumps(),
+                 threads: int = 1, first: int = 0):
+    """Price, pathwise Delta/Rho and (optionally) the five bump Greeks.
+
+    Returns {name: (value, std_err)} over the paths first .. first+n_paths-1."""
+    if bumps is not None:
+        pay, rec = scenario_payoffs(p, opt_type, n_steps, seed, n_paths, first, mode, fixings,
+                                    bumps, threads=threads)
+        samples = greek_samples(pay, p, bumps)
+    else:
+        rec = simulate(p, opt_type, n_steps, seed, first, n_paths, mode, fixings, threads=threads)
+        samples = {"price": rec[:, 3]}
+    samples["pw_delta"] = rec[:, 4]
+    samples["pw_rho"] = rec[:, 5]
+    return {k: tuple(float(v) for v in mean_se(y)) for k, y in samples.items()}

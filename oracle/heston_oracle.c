@@ -1,0 +1,401 @@
+/*
+ * heston_oracle.c -- plain FP64 reference for the Heston / Milstein Monte-Carlo
+ * path. TEST INFRASTRUCTURE ONLY: it is called by the test-suite, by the smoke
+ * check and by the benchmark's CPU-baseline leg, never by the product library.
+ * It shares no code with the GPU path.
+ *
+ * What it computes (one path at a time, in double precision, no blocking and
+ * no fusion):
+ *   - the Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw,
+ *     "Parallel Random Numbers: As Easy as 1, 2, 3", SC'11), used to draw the
+ *     two independent normals of every step by the Box-Muller transform;
+ *   - the correlated pair Z1 = Za, Z2 = rho Za + sqrt(1-rho^2) Zb
+ *     (paper, Background: algorithm "Generation of two correlated Normal
+ *     random variables");
+ *   - the Milstein scheme of the paper (Background, algorithm "Milstein
+ *     approximation under Heston model"): the log-price step carries no
+ *     correction term and the variance step carries 1/4 sigma^2 dt (Z2^2-1);
+ *     truncation either as the paper writes it (V <- max(V,0) after every step,
+ *     "absorption") or as full truncation (V+ = max(V,0) used in drift and
+ *     diffusion, the unclamped V carried);
+ *   - the discounted payoffs of European and arithmetic-Asian calls and puts
+ *     (Background, payoff definitions and risk-neutral pricing) and the
+ *     pathwise Delta and Rho estimators (Background, "Pathwise method for
+ *     greeks estimation": European estimators as printed, the Asian Rho with
+ *     the exact derivative of the discrete average);
+ *   - forward-mode (tangent) derivatives of each path's discounted payoff with
+ *     respect to (S0, v0, r, kappa, theta, sigma, rho), by the chain rule
+ *     carried step by step alongside the path.
+ *
+ * Readings taken where the paper is silent (stated again in the design notes):
+ *   - integer step loop j = 0..N-1 with dt = T/N;
+ *   - the step uses the variance at the start of the step;
+ *   - Za drives the price, Zb is mixed into the variance;
+ *   - stream layout: key = (lo32 seed, hi32 seed); counter =
+ *     (j>>1, lo32 path, hi32 path, 0); words 0,1 feed even steps and words 2,3
+ *     odd steps; uniform u = ((w >> 9) + 1/2) 2^-23, which is exact in single
+ *     and double precision and never 0 or 1;
+ *   - Za = sqrt(-2 ln ua) cos(2 pi ub), Zb = sqrt(-2 ln ua) sin(2 pi ub).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_REC 6    /* S_T, V_T, Sbar, discounted payoff, pathwise Delta, pathwise Rho */
+#define OR_TAN 8    /* discounted payoff, d/dS0, d/dv0, d/dr, d/dkappa, d/dtheta, d/dsigma, d/drho */
+
+typedef struct {
+    double S0, K, r, T, v0, kappa, theta, sigma, rho;
+} or_params;
+
+enum { OR_EURO_CALL = 0, OR_EURO_PUT = 1, OR_ASIAN_CALL = 2, OR_ASIAN_PUT = 3 };
+enum { OR_FULL_TRUNC = 0, OR_ABSORB = 1 };
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (SC'11): ten rounds of two 32x32->64 multiplies, with the
+ * two-word key advanced by the Weyl constants between rounds.                */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t prod0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(prod1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)prod1;
+        uint32_t n2 = (uint32_t)(prod0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)prod0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+double or_uniform(uint32_t w)
+{
+    return ((double)(w >> 9) + 0.5) * 0x1p-23;
+}
+
+/* The two independent standard normals of step `step` of path `path`. */
+void or_normals(uint64_t seed, uint64_t path, uint32_t step, double *za, double *zb)
+{
+    uint32_t ctr[4] = { step >> 1, (uint32_t)path, (uint32_t)(path >> 32), 0u };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t w[4];
+    or_philox4x32_10(ctr, key, w);
+    uint32_t wa = (step & 1u) ? w[2] : w[0];
+    uint32_t wb = (step & 1u) ? w[3] : w[1];
+    double ua = or_uniform(wa);
+    double ub = or_uniform(wb);
+    double radius = sqrt(-2.0 * log(ua));
+    double angle = 2.0 * M_PI * ub;
+    *za = radius * cos(angle);
+    *zb = radius * sin(angle);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Where the step's normals come from: the Philox stream, or caller arrays
+ * (row-major [n_paths][n_steps], used for quasi-random normals).            */
+typedef struct {
+    uint64_t seed;
+    const double *za; /* NULL -> Philox */
+    const double *zb;
+    uint32_t n_steps;
+} or_source;
+
+static void step_normals(const or_source *src, uint64_t path, uint64_t row, uint32_t j,
+                         double *za, double *zb)
+{
+    if (src->za) {
+        *za = src->za[row * src->n_steps + j];
+        *zb = src->zb[row * src->n_steps + j];
+    } else {
+        or_normals(src->seed, path, j, za, zb);
+    }
+}
+
+static int is_asian(int type) { return type == OR_ASIAN_CALL || type == OR_ASIAN_PUT; }
+static int is_call(int type) { return type == OR_EURO_CALL || type == OR_ASIAN_CALL; }
+
+/* One path of the Milstein scheme; writes the OR_REC record.
+ * fix[j] != 0 marks step j (1..N) as an Asian fixing date; n_fix = |F|.     */
+static void sim_path(const or_params *P, int type, uint32_t N, const uint8_t *fix, uint32_t n_fix,
+                     int mode, const or_source *src, uint64_t path, uint64_t row, double *rec)
+{
+    const double dt = P->T / (double)N;
+    const double rho_bar = sqrt(1.0 - P->rho * P->rho);
+    double S = P->S0;
+    double V = P->v0;
+    double A = 0.0; /* sum of S at fixing dates        */
+    double B = 0.0; /* sum of t_i S at fixing dates    */
+    for (uint32_t j = 0; j < N; ++j) {
+        double za, zb;
+        step_normals(src, path, row, j, &za, &zb);
+        double z1 = za;
+        double z2 = P->rho * za + rho_bar * zb;
+        double vp = V > 0.0 ? V : 0.0;
+        S = S * exp((P->r - 0.5 * vp) * dt + sqrt(vp * dt) * z1);
+        double vb = (mode == OR_FULL_TRUNC) ? V : vp;
+        V = vb + P->kappa * (P->theta - vp) * dt + P->sigma * sqrt(vp * dt) * z2
+            + 0.25 * P->sigma * P->sigma * dt * (z2 * z2 - 1.0);
+        if (mode == OR_ABSORB && V < 0.0)
+            V = 0.0;
+        if (fix[j + 1]) {
+            double t = (double)(j + 1) * dt;
+            A += S;
+            B += t * S;
+        }
+    }
+    const double D = exp(-P->r * P->T);
+    double Sbar = is_asian(type) ? A / (double)n_fix : S;
+    double pay, dpw, rpw;
+    if (is_call(type)) {
+        int itm = Sbar > P->K;
+        pay = D * (itm ? Sbar - P->K : 0.0);
+        dpw = itm ? D * Sbar / P->S0 : 0.0;
+        if (is_asian(type))
+            rpw = itm ? D * (B / (double)n_fix - P->T * (Sbar - P->K)) : 0.0;
+        else
+            rpw = itm ? D * P->K * P->T : 0.0;
+    } else {
+        int itm = Sbar < P->K;
+        pay = D * (itm ? P->K - Sbar : 0.0);
+        dpw = itm ? -D * Sbar / P->S0 : 0.0;
+        if (is_asian(type))
+            rpw = itm ? D * (-B / (double)n_fix - P->T * (P->K - Sbar)) : 0.0;
+        else
+            rpw = itm ? -D * P->K * P->T : 0.0;
+    }
+    rec[0] = S;
+    rec[1] = V;
+    rec[2] = Sbar;
+    rec[3] = pay;
+    rec[4] = dpw;
+    rec[5] = rpw;
+}
+
+/* Forward-mode derivatives of one path's discounted payoff with respect to
+ * theta = (S0, v0, r, kappa, theta, sigma, rho).  Every state variable carries
+ * its 7-vector of partial derivatives; each line differentiates the matching
+ * line of sim_path by the chain rule.  Conventions at the non-smooth points:
+ * d max(y,0)/dy = 1{y > 0}, and d sqrt(V+ dt)/dV = 0 where V+ = 0.          */
+#define NP 7
+static void tan_path(const or_params *P, int type, uint32_t N, const uint8_t *fix, uint32_t n_fix,
+                     int mode, const or_source *src, uint64_t path, uint64_t row, double *out)
+{
+    enum { I_S0 = 0, I_V0, I_R, I_KAPPA, I_THETA, I_SIGMA, I_RHO };
+    const double dt = P->T / (double)N;
+    const double rho_bar = sqrt(1.0 - P->rho * P->rho);
+    const double drho_bar = -P->rho / rho_bar; /* d rho_bar / d rho */
+    double S = P->S0, dS[NP] = { 0 };
+    double V = P->v0, dV[NP] = { 0 };
+    double A = 0.0, dA[NP] = { 0 };
+    dS[I_S0] = 1.0;
+    dV[I_V0] = 1.0;
+    for (uint32_t j = 0; j < N; ++j) {
+        double za, zb;
+        step_normals(src, path, row, j, &za, &zb);
+        double z1 = za;
+        double z2 = P->rho * za + rho_bar * zb;
+        double dz2[NP] = { 0 };
+        dz2[I_RHO] = za + drho_bar * zb;
+
+        int pos = V > 0.0;
+        double vp = pos ? V : 0.0;
+        double dvp[NP];
+        for (int k = 0; k < NP; ++k)
+            dvp[k] = pos ? dV[k] : 0.0;
+        double sq = sqrt(vp * dt);                  /* sqrt(V+ dt)          */
+        double dsq_dvp = pos ? dt / (2.0 * sq) : 0.0; /* d sqrt(V+ dt)/d V+   */
+
+        /* log-price increment and its derivatives */
+        double inc = (P->r - 0.5 * vp) * dt + sq * z1;
+        double dinc[NP];
+        for (int k = 0; k < NP; ++k)
+            dinc[k] = -0.5 * dvp[k] * dt + dsq_dvp * dvp[k] * z1;
+        dinc[I_R] += dt;
+        double g = exp(inc);
+        double Snew = S * g;
+        for (int k = 0; k < NP; ++k)
+            dS[k] = g * dS[k] + Snew * dinc[k];
+        S = Snew;
+
+        /* variance step and its derivatives */
+        double vb = (mode == OR_FULL_TRUNC) ? V : vp;
+        double Vnew = vb + P->kappa * (P->theta - vp) * dt + P->sigma * sq * z2
+                      + 0.25 * P->sigma * P->sigma * dt * (z2 * z2 - 1.0);
+        double dVnew[NP];
+        for (int k = 0; k < NP; ++k) {
+            double dvb = (mode == OR_FULL_TRUNC) ? dV[k] : dvp[k];
+            dVnew[k] = dvb - P->kappa * dvp[k] * dt + P->sigma * dsq_dvp * dvp[k] * z2
+                       + P->sigma * sq * dz2[k] + 0.5 * P->sigma * P->sigma * dt * z2 * dz2[k];
+        }
+        dVnew[I_KAPPA] += (P->theta - vp) * dt;
+        dVnew[I_THETA] += P->kappa * dt;
+        dVnew[I_SIGMA] += sq * z2 + 0.5 * P->sigma * dt * (z2 * z2 - 1.0);
+        if (mode == OR_ABSORB && Vnew <= 0.0) {
+            Vnew = 0.0;
+            for (int k = 0; k < NP; ++k)
+                dVnew[k] = 0.0;
+        }
+        V = Vnew;
+        for (int k = 0; k < NP; ++k)
+            dV[k] = dVnew[k];
+
+        if (fix[j + 1]) {
+            A += S;
+            for (int k = 0; k < NP; ++k)
+                dA[k] += dS[k];
+        }
+    }
+    const double D = exp(-P->r * P->T);
+    double X, dX[NP];
+    if (is_asian(type)) {
+        X = A / (double)n_fix;
+        for (int k = 0; k < NP; ++k)
+            dX[k] = dA[k] / (double)n_fix;
+    } else {
+        X = S;
+        for (int k = 0; k < NP; ++k)
+            dX[k] = dS[k];
+    }
+    double sgn = is_call(type) ? 1.0 : -1.0;
+    double intrinsic = sgn * (X - P->K);
+    int itm = intrinsic > 0.0;
+    double pay = D * (itm ? intrinsic : 0.0);
+    out[0] = pay;
+    for (int k = 0; k < NP; ++k)
+        out[1 + k] = itm ? D * sgn * dX[k] : 0.0;
+    out[1 + I_R] += -P->T * pay; /* the discount factor depends on r */
+}
+
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const or_params *P;
+    int type, mode, tangent;
+    uint32_t N, n_fix;
+    const uint8_t *fix;
+    const or_source *src;
+    uint64_t first, lo, hi;
+    double *out;
+} or_job;
+
+static void *run_job(void *arg)
+{
+    or_job *jb = (or_job *)arg;
+    for (uint64_t row = jb->lo; row < jb->hi; ++row) {
+        uint64_t path = jb->first + row;
+        if (jb->tangent)
+            tan_path(jb->P, jb->type, jb->N, jb->fix, jb->n_fix, jb->mode, jb->src, path, row,
+                     jb->out + row * OR_TAN);
+        else
+            sim_path(jb->P, jb->type, jb->N, jb->fix, jb->n_fix, jb->mode, jb->src, path, row,
+                     jb->out + row * OR_REC);
+    }
+    return NULL;
+}
+
+/* Runs paths first .. first+n_paths-1.  fix_steps lists the Asian fixing
+ * steps (values in 1..N, strictly increasing); NULL means every step for an
+ * Asian and is ignored for a European.  za/zb: NULL for the Philox stream,
+ * else caller normals [n_paths][N].  Returns 0, or -1 on a bad argument.    */
+static int run(const or_params *P, int type, uint32_t N, const uint32_t *fix_steps, uint32_t n_fix,
+               int mode, uint64_t seed, uint64_t first, uint64_t n_paths, const double *za,
+               const double *zb, int n_threads, int tangent, double *out)
+{
+    if (N == 0 || type < 0 || type > 3 || (mode != OR_FULL_TRUNC && mode != OR_ABSORB))
+        return -1;
+    uint8_t *fix = (uint8_t *)calloc((size_t)N + 1, 1);
+    if (!fix)
+        return -1;
+    uint32_t nf = 0;
+    if (is_asian(type) && fix_steps) {
+        for (uint32_t i = 0; i < n_fix; ++i) {
+            if (fix_steps[i] < 1 || fix_steps[i] > N || fix[fix_steps[i]]) {
+                free(fix);
+                return -1;
+            }
+            fix[fix_steps[i]] = 1;
+            ++nf;
+        }
+    } else if (is_asian(type)) {
+        for (uint32_t j = 1; j <= N; ++j)
+            fix[j] = 1;
+        nf = N;
+    } else {
+        fix[N] = 1;
+        nf = 1;
+    }
+    if (nf == 0) {
+        free(fix);
+        return -1;
+    }
+    or_source src = { seed, za, zb, N };
+    if (n_threads < 1)
+        n_threads = 1;
+    if ((uint64_t)n_threads > n_paths)
+        n_threads = n_paths > 0 ? (int)n_paths : 1;
+    pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    or_job *jobs = (or_job *)calloc((size_t)n_threads, sizeof(or_job));
+    for (int t = 0; t < n_threads; ++t) {
+        or_job jb = { P, type, mode, tangent, N, nf, fix, &src, first,
+                      n_paths * (uint64_t)t / (uint64_t)n_threads,
+                      n_paths * (uint64_t)(t + 1) / (uint64_t)n_threads, out };
+        jobs[t] = jb;
+        if (n_threads == 1)
+            run_job(&jobs[t]);
+        else
+            pthread_create(&th[t], NULL, run_job, &jobs[t]);
+    }
+    if (n_threads > 1)
+        for (int t = 0; t < n_threads; ++t)
+            pthread_join(th[t], NULL);
+    free(jobs);
+    free(th);
+    free(fix);
+    return 0;
+}
+
+int or_simulate(const or_params *P, int type, uint32_t N, const uint32_t *fix_steps, uint32_t n_fix,
+                int mode, uint64_t seed, uint64_t first, uint64_t n_paths, const double *za,
+                const double *zb, int n_threads, double *rec_out)
+{
+    return run(P, type, N, fix_steps, n_fix, mode, seed, first, n_paths, za, zb, n_threads, 0,
+               rec_out);
+}
+
+int or_tangent(const or_params *P, int type, uint32_t N, const uint32_t *fix_steps, uint32_t n_fix,
+               int mode, uint64_t seed, uint64_t first, uint64_t n_paths, const double *za,
+               const double *zb, int n_threads, double *tan_out)
+{
+    return run(P, type, N, fix_steps, n_fix, mode, seed, first, n_paths, za, zb, n_threads, 1,
+               tan_out);
+}
+
+/* Bulk Philox normals for tests: za/zb [n_paths][N] for paths first.. */
+void or_normals_block(uint64_t seed, uint64_t first, uint64_t n_paths, uint32_t N, double *za,
+                      double *zb)
+{
+    for (uint64_t p = 0; p < n_paths; ++p)
+        for (uint32_t j = 0; j < N; ++j)
+            or_normals(seed, first + p, j, &za[p * N + j], &zb[p * N + j]);
+}
+
+void or_philox_block(const uint32_t *ctr, const uint32_t *key, uint64_t n, uint32_t *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        or_philox4x32_10(ctr + 4 * i, key + 2 * i, out + 4 * i);
+}
