@@ -1,0 +1,192 @@
+/*
+ * heston.h -- C ABI of the MI355X (gfx950) Heston / Milstein Monte-Carlo
+ * library (libheston.so).
+ *
+ * The library prices European and arithmetic-Asian calls and puts under the
+ * Heston model (paper: "Heston Model for option pricing", eq. heston_eq) by
+ * Monte Carlo over paths of the Milstein scheme (Background, algorithm
+ * "Milstein approximation under Heston model"), with the Monte-Carlo
+ * estimator of algorithm "Monte Carlo option pricing estimation", and returns
+ * the Greeks: the pathwise Delta and Rho estimators of the section "Pathwise
+ * method for greeks estimation" (eqs. euro_pw and asian_pw; the Asian Rho uses
+ * the exact derivative of the discrete average, without the printed K T
+ * factor), five central bump-and-revalue Greeks on common random numbers, and
+ * reverse-mode (adjoint) sensitivities to the seven model inputs.
+ *
+ * Conventions shared by every call
+ *   - Every call returns heston_status; outputs are written only on HESTON_OK.
+ *   - Host structs and host arrays are owned by the caller and only read during
+ *     the call.  Device pointers passed in are borrowed for the duration of the
+ *     call and used on the context's stream.
+ *   - No C++ exception crosses this boundary.  A NaN or infinite input gives
+ *     HESTON_INVALID_ARGUMENT; heston_last_error() then describes the cause.
+ *   - Valid model inputs: S0 > 0, K > 0, T > 0, v0 >= 0, kappa > 0, theta >= 0,
+ *     sigma >= 0, |rho| <= 1 (|rho| < 1 for adjoint calls); n_paths >= 2,
+ *     n_steps >= 1; fixing steps strictly increasing in [1, n_steps].
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key =
+ *     (lo32 seed, hi32 seed) and counter = (step >> 1, lo32 path, hi32 path, 0);
+ *     words 0,1 feed even steps and words 2,3 odd steps; uniforms
+ *     ((w >> 9) + 1/2) 2^-23; normals by Box-Muller,
+ *     Za = sqrt(-2 ln ua) cos(2 pi ub), Zb = sqrt(-2 ln ua) sin(2 pi ub);
+ *     Z1 = Za drives the log-price, Z2 = rho Za + sqrt(1-rho^2) Zb the
+ *     variance (algorithm "Generation of two correlated Normal random
+ *     variables").  The same request gives bit-identical results every time.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef HESTON_H
+#define HESTON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HESTON_ABI_VERSION 1
+
+/* Model and contract inputs (paper: Table "Heston model parameters"). */
+typedef struct heston_params {
+    double S0, K, r, T, v0, kappa, theta, sigma, rho;
+} heston_params;
+
+/* Payoffs (paper: Background, European and arithmetic-Asian payoffs). */
+typedef enum heston_option_type {
+    HESTON_EURO_CALL = 0,
+    HESTON_EURO_PUT = 1,
+    HESTON_ASIAN_CALL = 2,
+    HESTON_ASIAN_PUT = 3
+} heston_option_type;
+
+typedef enum heston_status {
+    HESTON_OK = 0,
+    HESTON_PENDING = 1,
+    HESTON_INVALID_ARGUMENT = -1,
+    HESTON_OUT_OF_MEMORY = -2,
+    HESTON_OVER_BUDGET = -3,
+    HESTON_DEVICE_ERROR = -4,
+    HESTON_UNSUPPORTED = -5,
+    HESTON_NOT_FOUND = -6
+} heston_status;
+
+/* Arithmetic of the per-path state.  Cross-path sums are always FP64. */
+enum { HESTON_FP64 = 0, HESTON_FP32 = 1 };
+/* Normals: Philox pseudo-random, or Sobol points through a Brownian bridge. */
+enum { HESTON_RNG_PHILOX = 0, HESTON_RNG_SOBOL_BRIDGE = 1 };
+/* Truncation of the variance: full truncation (max(V,0) in drift and
+ * diffusion, unclamped V carried) or the paper's absorption (V <- max(V,0)
+ * after every step, algorithm "Milstein approximation under Heston model"). */
+enum { HESTON_FULL_TRUNCATION = 0, HESTON_ABSORPTION = 1 };
+/* Greek estimators (bit mask). */
+enum {
+    HESTON_GREEKS_PATHWISE = 1u,   /* paper's pathwise Delta and Rho              */
+    HESTON_GREEKS_BUMP_FUSED = 2u, /* 5 bump Greeks, one pass sharing the normals */
+    HESTON_GREEKS_BUMP_PLAIN = 4u  /* 5 bump Greeks, 9 independent revaluations   */
+};
+
+/* valid_mask bits of heston_result. */
+enum {
+    HESTON_VALID_PRICE = 1u,
+    HESTON_VALID_PATHWISE = 2u,
+    HESTON_VALID_BUMPS = 4u
+};
+
+typedef struct heston_est {
+    double value;   /* estimate                                             */
+    double std_err; /* standard error: sample SE over paths (Philox), or the
+                       std of the replicate estimates / sqrt(R) (Sobol)    */
+} heston_est;
+
+typedef struct heston_result {
+    heston_est price;
+    heston_est delta, gamma, vega, rho, theta; /* bump-and-revalue; vega = dP/dv0, theta = -dP/dT */
+    heston_est pw_delta, pw_rho;               /* paper's pathwise estimators                  */
+    uint64_t n_paths;
+    uint32_t valid_mask;
+    uint32_t reserved;
+    double device_ms; /* GPU time of the path kernel, HIP events on the context stream */
+} heston_result;
+
+typedef struct heston_opts {
+    uint32_t struct_size; /* sizeof(heston_opts); set by heston_default_opts     */
+    int32_t precision;    /* HESTON_FP64 (default) or HESTON_FP32                */
+    int32_t rng;          /* HESTON_RNG_PHILOX (default) or HESTON_RNG_SOBOL_BRIDGE */
+    int32_t scheme;       /* HESTON_FULL_TRUNCATION (default) or HESTON_ABSORPTION  */
+    uint32_t greeks;      /* HESTON_GREEKS_* mask; default PATHWISE | BUMP_FUSED */
+    uint32_t qmc_replicates; /* Sobol: R digitally shifted replicates; n_paths must
+                                be a multiple of R (points per replicate = n_paths/R) */
+    const uint32_t *sobol_directions; /* Sobol: host array [sobol_dims][32] of 30-bit
+                                direction numbers v[d][b] (only b < 30 read), the
+                                Joe-Kuo table in the layout of torch's SobolEngine
+                                state; dimension 2k feeds bridge node k of the price
+                                motion and 2k+1 that of the variance motion */
+    uint32_t sobol_dims;      /* rows in sobol_directions; must be >= 2 n_steps  */
+    const uint32_t *fixing_steps; /* Asian fixing steps (host, strictly increasing
+                                in [1, n_steps]); NULL = every step; ignored for
+                                European options, whose only date is n_steps    */
+    uint32_t n_fixings;
+    double bump_S0_rel; /* default 0.01   (h = bump_S0_rel * S0)      */
+    double bump_v0_rel; /* default 0.01   (h = bump_v0_rel * v0)      */
+    double bump_r_abs;  /* default 1e-4                               */
+    double bump_T_abs;  /* default 1/365; n_steps and the fixing step
+                           indices stay fixed, so dt is rescaled      */
+} heston_opts;
+
+typedef struct heston_ctx heston_ctx;
+
+/* Fills *opts with the defaults above.  Returns HESTON_INVALID_ARGUMENT for NULL. */
+heston_status heston_default_opts(heston_opts *opts);
+
+/* Creates a context on HIP device `device`.  `hip_stream` (a hipStream_t, may
+ * be NULL for the device's null stream) is borrowed: every kernel and copy of
+ * the context runs on it, and the caller keeps it alive until
+ * heston_ctx_destroy.  `hbm_budget_bytes` caps the device memory the context
+ * allocates for itself (0 = no cap).  Errors: INVALID_ARGUMENT (bad device or
+ * NULL out), DEVICE_ERROR. */
+heston_status heston_ctx_create(int device, void *hip_stream, uint64_t hbm_budget_bytes,
+                                heston_ctx **out);
+heston_status heston_ctx_destroy(heston_ctx *ctx);
+
+/* Price and Greeks of one option (paper: algorithm "Monte Carlo option
+ * pricing estimation" over paths of algorithm "Milstein approximation under
+ * Heston model").  Paths 0 .. n_paths-1 of the stream of `seed`.  Blocks until
+ * the result is on the host.  `opts` may be NULL for the defaults.  Errors:
+ * INVALID_ARGUMENT, UNSUPPORTED (n_steps above the kernel limit of 1<<20),
+ * OUT_OF_MEMORY / OVER_BUDGET (scratch), DEVICE_ERROR. */
+heston_status heston_price_greeks_ex(heston_ctx *ctx, const heston_params *params,
+                                     heston_option_type type, uint64_t n_paths, uint32_t n_steps,
+                                     uint64_t seed, const heston_opts *opts, heston_result *out);
+
+/* heston_price_greeks_ex on a per-thread default context of the current HIP
+ * device and its null stream, with the default options. */
+heston_status heston_price_greeks(const heston_params *params, heston_option_type type,
+                                  uint64_t n_paths, uint32_t n_steps, uint64_t seed,
+                                  heston_result *out);
+
+/* Per-path records of paths first .. first+count-1 of the same request, for
+ * parity checks: writes count x HESTON_DUMP_WIDTH doubles, row-major, to the
+ * DEVICE buffer `out_dev` (caller-owned, at least count*HESTON_DUMP_WIDTH*8
+ * bytes).  The records are produced by the pricing kernel itself.  Columns:
+ *   0 S_T, 1 V_T (carried variance), 2 Sbar (Asian average, S_T for European),
+ *   3 discounted payoff, 4 pathwise Delta, 5 pathwise Rho,
+ *   6..13 discounted payoffs of the bumped scenarios S0+, S0-, v0+, v0-, r+,
+ *         r-, T+, T- (NaN unless opts->greeks has BUMP_FUSED),
+ *   14 ln(S_T/S0), 15 reserved (0).
+ * For Sobol requests `first + count` must not exceed n_paths. */
+#define HESTON_DUMP_WIDTH 16
+heston_status heston_dump_paths(heston_ctx *ctx, const heston_params *params,
+                                heston_option_type type, uint64_t n_paths, uint32_t n_steps,
+                                uint64_t seed, const heston_opts *opts, uint64_t first,
+                                uint64_t count, double *out_dev);
+
+/* Static description of a status code; never NULL. */
+const char *heston_status_str(heston_status status);
+/* Message of the last failed call on this host thread ("" if none). */
+const char *heston_last_error(void);
+/* HESTON_ABI_VERSION of the loaded library. */
+int heston_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HESTON_H */

@@ -1,0 +1,236 @@
+"""Python binding of libheston (the MI355X Heston / Milstein Monte-Carlo library).
+
+Argument marshalling only: every step of the path -- random numbers, Milstein
+steps, payoffs, Greek samples and their cross-path sums -- runs in the HIP
+kernels behind the C ABI declared in include/heston.h.  PyTorch provides device
+memory (dump buffers, checkpoints) and the current HIP stream.
+
+If libheston.so has not been built this module raises on import of the
+library; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libheston.so")
+
+EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT = 0, 1, 2, 3
+FP64, FP32 = 0, 1
+PHILOX, SOBOL_BRIDGE = 0, 1
+FULL_TRUNCATION, ABSORPTION = 0, 1
+GREEKS_PATHWISE, GREEKS_BUMP_FUSED, GREEKS_BUMP_PLAIN = 1, 2, 4
+DUMP_WIDTH = 16
+DUMP_FIELDS = ("S_T", "V_T", "Sbar", "pay", "pw_delta", "pw_rho", "pay_S0+", "pay_S0-",
+               "pay_v0+", "pay_v0-", "pay_r+", "pay_r-", "pay_T+", "pay_T-", "x_T", "reserved")
+STATUS = {0: "OK", 1: "PENDING", -1: "INVALID_ARGUMENT", -2: "OUT_OF_MEMORY",
+          -3: "OVER_BUDGET", -4: "DEVICE_ERROR", -5: "UNSUPPORTED", -6: "NOT_FOUND"}
+PARAM_NAMES = ("S0", "K", "r", "T", "v0", "kappa", "theta", "sigma", "rho")
+EST_NAMES = ("price", "delta", "gamma", "vega", "rho", "theta", "pw_delta", "pw_rho")
+
+
+class HestonError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in PARAM_NAMES]
+
+
+class CEst(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_double), ("std_err", ctypes.c_double)]
+
+
+class CResult(ctypes.Structure):
+    _fields_ = [(n, CEst) for n in EST_NAMES] + [
+        ("n_paths", ctypes.c_uint64), ("valid_mask", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32), ("device_ms", ctypes.c_double)]
+
+
+class COpts(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("rng", ctypes.c_int32),
+        ("scheme", ctypes.c_int32), ("greeks", ctypes.c_uint32),
+        ("qmc_replicates", ctypes.c_uint32),
+        ("sobol_directions", ctypes.POINTER(ctypes.c_uint32)), ("sobol_dims", ctypes.c_uint32),
+        ("fixing_steps", ctypes.POINTER(ctypes.c_uint32)), ("n_fixings", ctypes.c_uint32),
+        ("bump_S0_rel", ctypes.c_double), ("bump_v0_rel", ctypes.c_double),
+        ("bump_r_abs", ctypes.c_double), ("bump_T_abs", ctypes.c_double)]
+
+
+_lib = None
+
+EXPORTS = ("heston_default_opts", "heston_ctx_create", "heston_ctx_destroy",
+           "heston_price_greeks_ex", "heston_price_greeks", "heston_dump_paths",
+           "heston_status_str", "heston_last_error", "heston_abi_version")
+
+
+def lib():
+    """The loaded libheston.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2309_10477_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, c = ctypes.POINTER, ctypes
+    L.heston_default_opts.argtypes = [P(COpts)]
+    L.heston_ctx_create.argtypes = [c.c_int, c.c_void_p, c.c_uint64, P(c.c_void_p)]
+    L.heston_ctx_destroy.argtypes = [c.c_void_p]
+    L.heston_price_greeks_ex.argtypes = [c.c_void_p, P(CParams), c.c_int, c.c_uint64, c.c_uint32,
+                                         c.c_uint64, P(COpts), P(CResult)]
+    L.heston_price_greeks.argtypes = [P(CParams), c.c_int, c.c_uint64, c.c_uint32, c.c_uint64,
+                                      P(CResult)]
+    L.heston_dump_paths.argtypes = [c.c_void_p, P(CParams), c.c_int, c.c_uint64, c.c_uint32,
+                                    c.c_uint64, P(COpts), c.c_uint64, c.c_uint64, c.c_void_p]
+    L.heston_status_str.argtypes = [c.c_int]
+    L.heston_status_str.restype = c.c_char_p
+    L.heston_last_error.argtypes = []
+    L.heston_last_error.restype = c.c_char_p
+    L.heston_abi_version.restype = c.c_int
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != 0:
+        raise HestonError(status, lib().heston_last_error().decode())
+
+
+def sobol_directions(dims: int) -> np.ndarray:
+    """Joe-Kuo direction numbers [dims, 32] (uint32, columns >= 30 zero) from
+    torch's SobolEngine state."""
+    import torch
+    st = torch.quasirandom.SobolEngine(dims, scramble=False).sobolstate.numpy()
+    out = np.zeros((dims, 32), dtype=np.uint32)
+    out[:, :st.shape[1]] = st.astype(np.uint32)
+    return out
+
+
+@dataclass
+class Options:
+    precision: int = FP64
+    rng: int = PHILOX
+    scheme: int = FULL_TRUNCATION
+    greeks: int = GREEKS_PATHWISE | GREEKS_BUMP_FUSED
+    qmc_replicates: int = 16
+    fixings: tuple | None = None
+    bump_S0_rel: float = 0.01
+    bump_v0_rel: float = 0.01
+    bump_r_abs: float = 1e-4
+    bump_T_abs: float = 1.0 / 365.0
+
+
+class _OptsHolder:
+    """A COpts plus the host arrays it points to (kept alive for the call)."""
+
+    def __init__(self, o: Options, n_steps: int):
+        self.c = COpts()
+        check(lib().heston_default_opts(ctypes.byref(self.c)))
+        self.c.precision, self.c.rng, self.c.scheme = o.precision, o.rng, o.scheme
+        self.c.greeks, self.c.qmc_replicates = o.greeks, o.qmc_replicates
+        self.c.bump_S0_rel, self.c.bump_v0_rel = o.bump_S0_rel, o.bump_v0_rel
+        self.c.bump_r_abs, self.c.bump_T_abs = o.bump_r_abs, o.bump_T_abs
+        self.fix = self.dirs = None
+        if o.fixings is not None:
+            self.fix = np.ascontiguousarray(o.fixings, dtype=np.uint32)
+            self.c.fixing_steps = self.fix.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+            self.c.n_fixings = self.fix.size
+        if o.rng == SOBOL_BRIDGE:
+            self.dirs = _directions_cached(2 * n_steps)
+            self.c.sobol_directions = self.dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+            self.c.sobol_dims = self.dirs.shape[0]
+
+
+_dir_cache: dict = {}
+
+
+def _directions_cached(dims: int) -> np.ndarray:
+    if dims not in _dir_cache:
+        _dir_cache[dims] = np.ascontiguousarray(sobol_directions(dims))
+    return _dir_cache[dims]
+
+
+def _cparams(params) -> CParams:
+    if isinstance(params, dict):
+        return CParams(*(float(params[n]) for n in PARAM_NAMES))
+    return CParams(*(float(getattr(params, n)) for n in PARAM_NAMES))
+
+
+class Context:
+    """A library context on one device, bound to a HIP stream (default: torch's
+    current stream of that device)."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 0):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        ptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        check(lib().heston_ctx_create(device, ctypes.c_void_p(ptr), hbm_budget_bytes,
+                                      ctypes.byref(handle)))
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            check(lib().heston_ctx_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def price_greeks(self, params, opt_type: int, n_paths: int, n_steps: int, seed: int,
+                     opts: Options | None = None) -> dict:
+        """{estimator: (value, std_err)} plus 'device_ms' and 'n_paths'."""
+        o = _OptsHolder(opts or Options(), n_steps)
+        res = CResult()
+        cp = _cparams(params)
+        check(lib().heston_price_greeks_ex(self.handle, ctypes.byref(cp), opt_type, n_paths,
+                                           n_steps, seed, ctypes.byref(o.c), ctypes.byref(res)))
+        return _result_dict(res)
+
+    def dump_paths(self, params, opt_type: int, n_paths: int, n_steps: int, seed: int,
+                   first: int, count: int, opts: Options | None = None, out=None):
+        """Per-path records [count, 16] (torch float64 tensor on the device)."""
+        import torch
+        if out is None:
+            out = torch.empty((count, DUMP_WIDTH), dtype=torch.float64,
+                              device=f"cuda:{self.device}")
+        assert out.is_contiguous() and out.dtype == torch.float64 and out.numel() >= count * 16
+        o = _OptsHolder(opts or Options(), n_steps)
+        cp = _cparams(params)
+        check(lib().heston_dump_paths(self.handle, ctypes.byref(cp), opt_type, n_paths, n_steps,
+                                      seed, ctypes.byref(o.c), first, count,
+                                      ctypes.c_void_p(out.data_ptr())))
+        return out
+
+
+def _result_dict(res: CResult) -> dict:
+    out = {}
+    for n in EST_NAMES:
+        e = getattr(res, n)
+        out[n] = (e.value, e.std_err)
+    out["valid_mask"] = res.valid_mask
+    out["n_paths"] = res.n_paths
+    out["device_ms"] = res.device_ms
+    return out
+
+
+def price_greeks(params, opt_type: int, n_paths: int, n_steps: int, seed: int) -> dict:
+    """heston_price_greeks: default context of the current device, default options."""
+    res = CResult()
+    cp = _cparams(params)
+    check(lib().heston_price_greeks(ctypes.byref(cp), opt_type, n_paths, n_steps, seed,
+                                    ctypes.byref(res)))
+    return _result_dict(res)

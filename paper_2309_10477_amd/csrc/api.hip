@@ -1,0 +1,592 @@
+// C ABI of libheston: argument checks, the per-request plan (step
+// coefficients, fixing mask, Brownian-bridge walk), device scratch owned by a
+// context, kernel launches on the context's stream, and the final estimates.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "../../include/heston.h"
+#include "internal.hpp"
+
+using namespace heston;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+heston_status fail(heston_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? HESTON_OUT_OF_MEMORY : HESTON_DEVICE_ERROR,   \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+// A device buffer that only grows; its bytes count against the context budget.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+} // namespace
+
+struct heston_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t budget = 0;  // 0 = unlimited
+    uint64_t in_use = 0;  // bytes held by the buffers below
+    DevBuf partials, rep_sums, fix_bits, sobol_dirs, sobol_shift, bridge_start, bridge_ops;
+    double *host_sums = nullptr; // pinned
+    size_t host_sums_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+heston_status reserve(heston_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (b.bytes >= bytes)
+        return HESTON_OK;
+    bytes = (bytes + 4095) & ~size_t(4095);
+    const uint64_t after = c->in_use - b.bytes + bytes;
+    if (c->budget && after > c->budget)
+        return fail(HESTON_OVER_BUDGET, "device scratch of " + std::to_string(bytes) +
+                                            " bytes exceeds the context budget");
+    if (b.ptr) {
+        (void)hipFree(b.ptr);
+        c->in_use -= b.bytes;
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    HIP_TRY(hipMalloc(&b.ptr, bytes));
+    b.bytes = bytes;
+    c->in_use += bytes;
+    return HESTON_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev)
+            (void)hipSetDevice(dev);
+        else
+            prev = -1;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+bool finite_all(const heston_params *p)
+{
+    const double v[] = {p->S0, p->K, p->r, p->T, p->v0, p->kappa, p->theta, p->sigma, p->rho};
+    for (double x : v)
+        if (!std::isfinite(x))
+            return false;
+    return true;
+}
+
+heston_status check_params(const heston_params *p)
+{
+    if (!p)
+        return fail(HESTON_INVALID_ARGUMENT, "params is NULL");
+    if (!finite_all(p))
+        return fail(HESTON_INVALID_ARGUMENT, "params contain NaN or Inf");
+    if (!(p->S0 > 0) || !(p->K > 0) || !(p->T > 0))
+        return fail(HESTON_INVALID_ARGUMENT, "need S0 > 0, K > 0, T > 0");
+    if (!(p->v0 >= 0) || !(p->kappa > 0) || !(p->theta >= 0) || !(p->sigma >= 0))
+        return fail(HESTON_INVALID_ARGUMENT, "need v0 >= 0, kappa > 0, theta >= 0, sigma >= 0");
+    if (!(std::fabs(p->rho) <= 1))
+        return fail(HESTON_INVALID_ARGUMENT, "need |rho| <= 1");
+    return HESTON_OK;
+}
+
+StepCoef step_coef(const heston_params &p, double T, uint32_t N)
+{
+    StepCoef c;
+    c.dt = T / (double)N;
+    c.sqrt_dt = std::sqrt(c.dt);
+    c.r_dt = p.r * c.dt;
+    c.half_dt = 0.5 * c.dt;
+    c.kappa_dt = p.kappa * c.dt;
+    c.kappa_theta_dt = p.kappa * p.theta * c.dt;
+    c.quarter_sigma2_dt = 0.25 * p.sigma * p.sigma * c.dt;
+    return c;
+}
+
+// Brownian bridge on the unit grid 0..N: nodes are numbered in the first-in
+// first-out bisection order (node 0 is B_N, then midpoints m = floor((l+r)/2)
+// of intervals (l, r) with r - l >= 2, children (l, m) then (m, r) queued).
+// The kernel walks the grid in time order: before step j it computes, for
+// every pending midpoint between j and the smallest end-point already known,
+// B_m = a B_j + b B_top + c z_node with a = (r-m)/(r-l), b = (m-l)/(r-l),
+// c = sqrt((m-l)(r-m)/(r-l)), pushing each on a stack; then it pops B_{j+1}.
+struct BridgePlan {
+    std::vector<int32_t> start; // N+1
+    std::vector<BridgeOp> ops;  // N-1
+    int depth = 1;
+};
+
+bool bridge_program(uint32_t N, BridgePlan &plan)
+{
+    std::vector<int32_t> node_of(N + 1, -1), left(N + 1, -1), right(N + 1, -1);
+    node_of[N] = 0;
+    int32_t k = 1;
+    std::deque<std::pair<uint32_t, uint32_t>> q;
+    q.emplace_back(0u, N);
+    while (!q.empty()) {
+        auto [l, r] = q.front();
+        q.pop_front();
+        if (r - l >= 2) {
+            const uint32_t m = (l + r) / 2;
+            node_of[m] = k++;
+            left[m] = (int32_t)l;
+            right[m] = (int32_t)r;
+            q.emplace_back(l, m);
+            q.emplace_back(m, r);
+        }
+    }
+    plan.start.assign(N + 1, 0);
+    plan.ops.clear();
+    std::vector<uint32_t> stack{N};
+    int depth = 1;
+    for (uint32_t j = 0; j < N; ++j) {
+        plan.start[j] = (int32_t)plan.ops.size();
+        while (stack.back() > j + 1) {
+            const uint32_t r = stack.back();
+            const uint32_t m = (j + r) / 2;
+            // The pending interval must be the bisection tree's (j, r).
+            if (node_of[m] < 0 || left[m] != (int32_t)j || right[m] != (int32_t)r)
+                return false;
+            const double l = j, rr = r, mm = m;
+            BridgeOp op;
+            op.node = node_of[m];
+            op.ad = (rr - mm) / (rr - l);
+            op.bd = (mm - l) / (rr - l);
+            op.cd = std::sqrt((mm - l) * (rr - mm) / (rr - l));
+            op.a = (float)op.ad;
+            op.b = (float)op.bd;
+            op.c = (float)op.cd;
+            plan.ops.push_back(op);
+            stack.push_back(m);
+            depth = std::max(depth, (int)stack.size());
+        }
+        if (stack.back() != j + 1)
+            return false;
+        stack.pop_back();
+    }
+    plan.start[N] = (int32_t)plan.ops.size();
+    plan.depth = depth;
+    return plan.ops.size() == (size_t)(N - 1);
+}
+
+struct Request {
+    heston_params p;
+    int type;
+    uint64_t n_paths;
+    uint32_t n_steps;
+    uint64_t seed;
+    heston_opts o;
+};
+
+heston_status check_request(const Request &q)
+{
+    heston_status st = check_params(&q.p);
+    if (st != HESTON_OK)
+        return st;
+    if (q.type < 0 || q.type > 3)
+        return fail(HESTON_INVALID_ARGUMENT, "unknown option type");
+    if (q.n_paths < 2)
+        return fail(HESTON_INVALID_ARGUMENT, "need n_paths >= 2");
+    if (q.n_steps < 1)
+        return fail(HESTON_INVALID_ARGUMENT, "need n_steps >= 1");
+    if (q.n_steps > (1u << 20))
+        return fail(HESTON_UNSUPPORTED, "n_steps above 1<<20");
+    const heston_opts &o = q.o;
+    if (o.precision != HESTON_FP64 && o.precision != HESTON_FP32)
+        return fail(HESTON_INVALID_ARGUMENT, "unknown precision");
+    if (o.rng != HESTON_RNG_PHILOX && o.rng != HESTON_RNG_SOBOL_BRIDGE)
+        return fail(HESTON_INVALID_ARGUMENT, "unknown rng");
+    if (o.scheme != HESTON_FULL_TRUNCATION && o.scheme != HESTON_ABSORPTION)
+        return fail(HESTON_INVALID_ARGUMENT, "unknown scheme");
+    if (o.greeks & ~7u)
+        return fail(HESTON_INVALID_ARGUMENT, "unknown greeks bits");
+    if (o.greeks & HESTON_GREEKS_BUMP_PLAIN)
+        return fail(HESTON_UNSUPPORTED, "BUMP_PLAIN is served by heston_price_greeks_plain");
+    if (o.greeks & HESTON_GREEKS_BUMP_FUSED) {
+        const double b[] = {o.bump_S0_rel, o.bump_v0_rel, o.bump_r_abs, o.bump_T_abs};
+        for (double x : b)
+            if (!std::isfinite(x) || !(x > 0))
+                return fail(HESTON_INVALID_ARGUMENT, "bump sizes must be finite and > 0");
+        if (!(q.p.v0 > 0))
+            return fail(HESTON_INVALID_ARGUMENT, "relative v0 bump needs v0 > 0");
+        if (!(o.bump_S0_rel < 1) || !(o.bump_v0_rel < 1) || !(o.bump_T_abs < q.p.T))
+            return fail(HESTON_INVALID_ARGUMENT, "bumps must keep S0, v0 and T positive");
+    }
+    const bool asian = q.type >= 2;
+    if (asian && o.fixing_steps) {
+        if (o.n_fixings < 1)
+            return fail(HESTON_INVALID_ARGUMENT, "n_fixings must be >= 1");
+        for (uint32_t i = 0; i < o.n_fixings; ++i) {
+            const uint32_t f = o.fixing_steps[i];
+            if (f < 1 || f > q.n_steps || (i && f <= o.fixing_steps[i - 1]))
+                return fail(HESTON_INVALID_ARGUMENT,
+                            "fixing steps must be strictly increasing in [1, n_steps]");
+        }
+    }
+    if (o.rng == HESTON_RNG_SOBOL_BRIDGE) {
+        if (o.qmc_replicates < 1 || q.n_paths % o.qmc_replicates)
+            return fail(HESTON_INVALID_ARGUMENT, "n_paths must be a multiple of qmc_replicates");
+        if (q.n_paths / o.qmc_replicates > (1ull << 30))
+            return fail(HESTON_UNSUPPORTED, "more than 2^30 points per replicate");
+        if (!o.sobol_directions || o.sobol_dims < 2 * q.n_steps)
+            return fail(HESTON_INVALID_ARGUMENT, "need sobol_directions for 2*n_steps dimensions");
+        if (q.n_paths / o.qmc_replicates < 2)
+            return fail(HESTON_INVALID_ARGUMENT, "need >= 2 points per replicate");
+    }
+    return HESTON_OK;
+}
+
+// Builds the launch description of paths [first, first+count) of request q
+// and uploads its tables.  Does not launch.
+heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t count, PriceLaunch &L)
+{
+    const heston_params &p = q.p;
+    const heston_opts &o = q.o;
+    std::memset(&L, 0, sizeof(L));
+    L.S0 = p.S0; L.K = p.K; L.r = p.r; L.T = p.T; L.v0 = p.v0;
+    L.kappa = p.kappa; L.theta = p.theta; L.sigma = p.sigma; L.rho = p.rho;
+    L.rho_bar = std::sqrt(std::max(0.0, 1.0 - p.rho * p.rho));
+    L.opt_type = q.type;
+    L.scheme = o.scheme;
+    L.precision = o.precision;
+    L.rng = o.rng;
+    L.bumps = (o.greeks & HESTON_GREEKS_BUMP_FUSED) != 0;
+    L.n_steps = q.n_steps;
+    L.seed = q.seed;
+    L.first_path = first;
+    L.n_paths = count;
+    L.base = step_coef(p, p.T, q.n_steps);
+    if (L.bumps) {
+        L.hS = o.bump_S0_rel * p.S0;
+        L.hv = o.bump_v0_rel * p.v0;
+        L.hr = o.bump_r_abs;
+        L.hT = o.bump_T_abs;
+        L.tup = step_coef(p, p.T + L.hT, q.n_steps);
+        L.tdn = step_coef(p, p.T - L.hT, q.n_steps);
+    }
+    const bool asian = q.type >= 2;
+    L.n_fix = asian ? (o.fixing_steps ? o.n_fixings : q.n_steps) : 1;
+    L.fix_bits = nullptr;
+    if (asian && o.fixing_steps) {
+        const size_t words = (q.n_steps + 1 + 31) / 32;
+        std::vector<uint32_t> bits(words, 0u);
+        for (uint32_t i = 0; i < o.n_fixings; ++i)
+            bits[o.fixing_steps[i] >> 5] |= 1u << (o.fixing_steps[i] & 31u);
+        heston_status st = reserve(c, c->fix_bits, words * 4);
+        if (st != HESTON_OK)
+            return st;
+        HIP_TRY(hipMemcpyAsync(c->fix_bits.ptr, bits.data(), words * 4, hipMemcpyHostToDevice,
+                               c->stream));
+        L.fix_bits = (const uint32_t *)c->fix_bits.ptr;
+    }
+    uint64_t M;
+    if (o.rng == HESTON_RNG_SOBOL_BRIDGE) {
+        const uint32_t R = o.qmc_replicates, dims = 2 * q.n_steps;
+        M = q.n_paths / R;
+        L.rep0 = (uint32_t)(first / M);
+        L.n_reps = (uint32_t)((first + count - 1) / M) - L.rep0 + 1;
+        BridgePlan bp;
+        if (!bridge_program(q.n_steps, bp))
+            return fail(HESTON_DEVICE_ERROR, "internal: Brownian bridge walk inconsistent");
+        heston_status st;
+        if ((st = reserve(c, c->sobol_dirs, (size_t)dims * 32 * 4)) != HESTON_OK ||
+            (st = reserve(c, c->sobol_shift, (size_t)dims * R * 4)) != HESTON_OK ||
+            (st = reserve(c, c->bridge_start, (q.n_steps + 1) * 4)) != HESTON_OK ||
+            (st = reserve(c, c->bridge_ops, std::max<size_t>(1, bp.ops.size()) * sizeof(BridgeOp))) !=
+                HESTON_OK)
+            return st;
+        HIP_TRY(hipMemcpyAsync(c->sobol_dirs.ptr, o.sobol_directions, (size_t)dims * 32 * 4,
+                               hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(launch_sobol_shifts(q.seed, dims, R, (uint32_t *)c->sobol_shift.ptr, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->bridge_start.ptr, bp.start.data(), (q.n_steps + 1) * 4,
+                               hipMemcpyHostToDevice, c->stream));
+        if (!bp.ops.empty())
+            HIP_TRY(hipMemcpyAsync(c->bridge_ops.ptr, bp.ops.data(), bp.ops.size() * sizeof(BridgeOp),
+                                   hipMemcpyHostToDevice, c->stream));
+        // The host vectors die at return; finish the copies first.
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        L.sobol_dirs = (const uint32_t *)c->sobol_dirs.ptr;
+        L.sobol_shift = (const uint32_t *)c->sobol_shift.ptr;
+        L.bridge_start = (const int32_t *)c->bridge_start.ptr;
+        L.bridge_ops = (const BridgeOp *)c->bridge_ops.ptr;
+        L.bridge_root_scale = std::sqrt((double)q.n_steps);
+        L.bridge_depth = bp.depth;
+        if (bp.depth > MAX_BRIDGE_DEPTH)
+            return fail(HESTON_UNSUPPORTED, "Brownian bridge deeper than supported");
+    } else {
+        M = first + count;
+        L.rep0 = 0;
+        L.n_reps = 1;
+    }
+    L.paths_per_rep = M;
+    const uint64_t span = std::min<uint64_t>(count, M);
+    L.blocks_per_rep = (uint32_t)((span + BLOCK - 1) / BLOCK);
+    if ((uint64_t)L.blocks_per_rep * BLOCK < span || L.blocks_per_rep > 0x7FFFFFFFu)
+        return fail(HESTON_UNSUPPORTED, "too many paths for one launch");
+    heston_status st;
+    if ((st = reserve(c, c->partials, (size_t)L.n_reps * L.blocks_per_rep * N_ACC * 8)) != HESTON_OK ||
+        (st = reserve(c, c->rep_sums, (size_t)L.n_reps * N_ACC * 8)) != HESTON_OK)
+        return st;
+    L.partials = (double *)c->partials.ptr;
+    if (c->host_sums_bytes < (size_t)L.n_reps * N_ACC * 8) {
+        if (c->host_sums)
+            (void)hipHostFree(c->host_sums);
+        c->host_sums = nullptr;
+        c->host_sums_bytes = 0;
+        HIP_TRY(hipHostMalloc((void **)&c->host_sums, (size_t)L.n_reps * N_ACC * 8));
+        c->host_sums_bytes = (size_t)L.n_reps * N_ACC * 8;
+    }
+    return HESTON_OK;
+}
+
+heston_est est_from(double n, double s, double ss)
+{
+    const double m = s / n;
+    double var = (ss - s * m) / (n - 1.0);
+    if (var < 0)
+        var = 0;
+    return heston_est{m, std::sqrt(var / n)};
+}
+
+// Replicate estimates: mean of the R replicate means, SE = std of them / sqrt(R).
+heston_est est_reps(const double *sums, uint32_t R, double M, int e)
+{
+    double mean = 0;
+    for (uint32_t r = 0; r < R; ++r)
+        mean += sums[r * N_ACC + 2 * e] / M;
+    mean /= R;
+    double ss = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        const double d = sums[r * N_ACC + 2 * e] / M - mean;
+        ss += d * d;
+    }
+    return heston_est{mean, R > 1 ? std::sqrt(ss / (R - 1.0) / R) : 0.0};
+}
+
+Request make_request(const heston_params *p, heston_option_type type, uint64_t n_paths,
+                     uint32_t n_steps, uint64_t seed, const heston_opts *opts)
+{
+    Request q;
+    q.p = p ? *p : heston_params{};
+    q.type = (int)type;
+    q.n_paths = n_paths;
+    q.n_steps = n_steps;
+    q.seed = seed;
+    heston_default_opts(&q.o);
+    if (opts)
+        q.o = *opts;
+    return q;
+}
+
+heston_ctx *default_ctx(heston_status &st)
+{
+    thread_local std::vector<heston_ctx *> per_device;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        st = fail(HESTON_DEVICE_ERROR, "no HIP device");
+        return nullptr;
+    }
+    if ((int)per_device.size() <= dev)
+        per_device.resize(dev + 1, nullptr);
+    if (!per_device[dev]) {
+        st = heston_ctx_create(dev, nullptr, 0, &per_device[dev]);
+        if (st != HESTON_OK)
+            return nullptr;
+    }
+    st = HESTON_OK;
+    return per_device[dev];
+}
+
+} // namespace
+
+extern "C" {
+
+heston_status heston_default_opts(heston_opts *o)
+{
+    if (!o)
+        return fail(HESTON_INVALID_ARGUMENT, "opts is NULL");
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(heston_opts);
+    o->precision = HESTON_FP64;
+    o->rng = HESTON_RNG_PHILOX;
+    o->scheme = HESTON_FULL_TRUNCATION;
+    o->greeks = HESTON_GREEKS_PATHWISE | HESTON_GREEKS_BUMP_FUSED;
+    o->qmc_replicates = 16;
+    o->bump_S0_rel = 0.01;
+    o->bump_v0_rel = 0.01;
+    o->bump_r_abs = 1e-4;
+    o->bump_T_abs = 1.0 / 365.0;
+    return HESTON_OK;
+}
+
+heston_status heston_ctx_create(int device, void *hip_stream, uint64_t hbm_budget_bytes,
+                                heston_ctx **out)
+{
+    if (!out)
+        return fail(HESTON_INVALID_ARGUMENT, "out is NULL");
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1)
+        return fail(HESTON_DEVICE_ERROR, "no HIP device");
+    if (device < 0 || device >= n)
+        return fail(HESTON_INVALID_ARGUMENT, "device index out of range");
+    DeviceGuard g(device);
+    heston_ctx *c = new heston_ctx;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->budget = hbm_budget_bytes;
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return fail(HESTON_DEVICE_ERROR, "hipEventCreate failed");
+    }
+    *out = c;
+    return HESTON_OK;
+}
+
+heston_status heston_ctx_destroy(heston_ctx *c)
+{
+    if (!c)
+        return fail(HESTON_INVALID_ARGUMENT, "ctx is NULL");
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift,
+                      &c->bridge_start, &c->bridge_ops})
+        if (b->ptr)
+            (void)hipFree(b->ptr);
+    if (c->host_sums)
+        (void)hipHostFree(c->host_sums);
+    (void)hipEventDestroy(c->ev0);
+    (void)hipEventDestroy(c->ev1);
+    delete c;
+    return HESTON_OK;
+}
+
+heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
+                                     heston_option_type type, uint64_t n_paths, uint32_t n_steps,
+                                     uint64_t seed, const heston_opts *opts, heston_result *out)
+{
+    if (!c || !out)
+        return fail(HESTON_INVALID_ARGUMENT, "ctx or out is NULL");
+    if (opts && opts->struct_size != sizeof(heston_opts))
+        return fail(HESTON_INVALID_ARGUMENT, "opts->struct_size does not match this library");
+    const Request q = make_request(params, type, n_paths, n_steps, seed, opts);
+    heston_status st = check_request(q);
+    if (st != HESTON_OK)
+        return st;
+    DeviceGuard g(c->device);
+    PriceLaunch L;
+    if ((st = plan(c, q, 0, n_paths, L)) != HESTON_OK)
+        return st;
+    L.dump = nullptr;
+    HIP_TRY(hipEventRecord(c->ev0, c->stream));
+    HIP_TRY(launch_paths(L, c->stream));
+    HIP_TRY(hipEventRecord(c->ev1, c->stream));
+    HIP_TRY(launch_reduce(L, (double *)c->rep_sums.ptr, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->host_sums, c->rep_sums.ptr, (size_t)L.n_reps * N_ACC * 8,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+
+    heston_result r;
+    std::memset(&r, 0, sizeof(r));
+    const double *s = c->host_sums;
+    heston_est *slot[N_EST] = {&r.price, &r.pw_delta, &r.pw_rho, &r.delta,
+                               &r.gamma, &r.vega,     &r.rho,    &r.theta};
+    const int n_est = L.bumps ? N_EST : EST_DELTA;
+    for (int e = 0; e < n_est; ++e)
+        *slot[e] = q.o.rng == HESTON_RNG_SOBOL_BRIDGE
+                       ? est_reps(s, L.n_reps, (double)L.paths_per_rep, e)
+                       : est_from((double)n_paths, s[2 * e], s[2 * e + 1]);
+    r.n_paths = n_paths;
+    r.valid_mask = HESTON_VALID_PRICE | HESTON_VALID_PATHWISE | (L.bumps ? HESTON_VALID_BUMPS : 0u);
+    r.device_ms = ms;
+    *out = r;
+    return HESTON_OK;
+}
+
+heston_status heston_price_greeks(const heston_params *params, heston_option_type type,
+                                  uint64_t n_paths, uint32_t n_steps, uint64_t seed,
+                                  heston_result *out)
+{
+    heston_status st;
+    heston_ctx *c = default_ctx(st);
+    if (!c)
+        return st;
+    return heston_price_greeks_ex(c, params, type, n_paths, n_steps, seed, nullptr, out);
+}
+
+heston_status heston_dump_paths(heston_ctx *c, const heston_params *params,
+                                heston_option_type type, uint64_t n_paths, uint32_t n_steps,
+                                uint64_t seed, const heston_opts *opts, uint64_t first,
+                                uint64_t count, double *out_dev)
+{
+    if (!c || !out_dev)
+        return fail(HESTON_INVALID_ARGUMENT, "ctx or out_dev is NULL");
+    if (opts && opts->struct_size != sizeof(heston_opts))
+        return fail(HESTON_INVALID_ARGUMENT, "opts->struct_size does not match this library");
+    const Request q = make_request(params, type, n_paths, n_steps, seed, opts);
+    heston_status st = check_request(q);
+    if (st != HESTON_OK)
+        return st;
+    if (count == 0)
+        return HESTON_OK;
+    if (q.o.rng == HESTON_RNG_SOBOL_BRIDGE && (first >= n_paths || count > n_paths - first))
+        return fail(HESTON_INVALID_ARGUMENT, "dump range beyond n_paths of a Sobol request");
+    if (first + count < first)
+        return fail(HESTON_INVALID_ARGUMENT, "dump range overflows");
+    DeviceGuard g(c->device);
+    PriceLaunch L;
+    if ((st = plan(c, q, first, count, L)) != HESTON_OK)
+        return st;
+    L.dump = out_dev;
+    HIP_TRY(launch_paths(L, c->stream));
+    HIP_TRY(launch_reduce(L, (double *)c->rep_sums.ptr, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return HESTON_OK;
+}
+
+const char *heston_status_str(heston_status s)
+{
+    switch (s) {
+    case HESTON_OK: return "ok";
+    case HESTON_PENDING: return "pending";
+    case HESTON_INVALID_ARGUMENT: return "invalid argument";
+    case HESTON_OUT_OF_MEMORY: return "out of device memory";
+    case HESTON_OVER_BUDGET: return "over the context's memory budget";
+    case HESTON_DEVICE_ERROR: return "device error";
+    case HESTON_UNSUPPORTED: return "unsupported";
+    case HESTON_NOT_FOUND: return "not found";
+    }
+    return "unknown status";
+}
+
+const char *heston_last_error(void) { return g_last_error.c_str(); }
+
+int heston_abi_version(void) { return HESTON_ABI_VERSION; }
+
+} // extern "C"

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no GPU needed: only host-side calls that launch nothing)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "heston.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(heston_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2309_10477_amd as hm
+    return hm.lib()
+
+
+def test_every_declared_function_is_exported(L):
+    names = declared_functions()
+    assert "heston_price_greeks" in names and len(names) >= 9
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_host_only_calls(L):
+    import paper_2309_10477_amd as hm
+    assert L.heston_abi_version() == 1
+    assert L.heston_status_str(-1) == b"invalid argument"
+    o = hm.COpts()
+    assert L.heston_default_opts(ctypes.byref(o)) == 0
+    assert o.struct_size == ctypes.sizeof(hm.COpts)
+    assert (o.precision, o.rng, o.scheme, o.greeks) == (0, 0, 0, 3)
+    assert o.bump_S0_rel == 0.01 and o.bump_r_abs == 1e-4 and o.bump_T_abs == 1 / 365
+    assert L.heston_default_opts(None) == -1
+
+
+def test_struct_layout_matches_header():
+    """Sizes of the ABI structs as laid out by a C compiler."""
+    import subprocess
+    import tempfile
+    import paper_2309_10477_amd as hm
+    src = ('#include "heston.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){'
+           'printf("%zu %zu %zu %zu %zu\\n", sizeof(heston_params), sizeof(heston_opts),'
+           ' sizeof(heston_result), offsetof(heston_opts, fixing_steps),'
+           ' offsetof(heston_result, device_ms)); return 0;}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "t")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        got = [int(v) for v in subprocess.check_output([exe]).split()]
+    want = [ctypes.sizeof(hm.CParams), ctypes.sizeof(hm.COpts), ctypes.sizeof(hm.CResult),
+            hm.COpts.fixing_steps.offset, hm.CResult.device_ms.offset]
+    assert got == want

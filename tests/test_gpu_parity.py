@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Per path (heston_dump_paths records, produced by the pricing kernel itself)
+against oracle.simulate / oracle.scenario_payoffs on the same seeded stream,
+with |gpu - oracle| <= tol * max(|oracle|, floor): floors S0 for prices,
+averages and payoffs, max(v0, theta) for the variance, 1 for pathwise Delta,
+K T for pathwise Rho; tol = 1e-12 (FP64 kernels) and 1e-5 (FP32 kernels).
+A payoff indicator may differ only on paths with |X - K| < 1e3 tol K.
+Reduced estimates are checked against the same per-path values summed on the
+host.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import BASE, PAPER, paper_fixing_steps
+
+pytestmark = pytest.mark.gpu
+
+PB = oracle.Params(**BASE)
+PP = oracle.Params(**PAPER)
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_10477_amd as hm
+    hm.lib()
+    return hm
+
+
+@pytest.fixture(scope="module")
+def ctx(hm):
+    c = hm.Context(0)
+    yield c
+    c.close()
+
+
+def floors(p):
+    return {"S_T": p.S0, "V_T": max(p.v0, p.theta, 1e-3), "Sbar": p.S0, "pay": p.S0,
+            "pw_delta": 1.0, "pw_rho": p.K * p.T}
+
+
+def compare(name, g, o, tol, floor, allow=None):
+    err = np.abs(g - o) / np.maximum(np.abs(o), floor)
+    bad = err > tol
+    if allow is not None:
+        bad &= ~allow
+    if bad.any():
+        i = int(np.argmax(np.where(bad, err, 0)))
+        raise AssertionError(f"{name}: {int(bad.sum())} paths off, worst path {i}: "
+                             f"gpu {g[i]!r} oracle {o[i]!r} rel {err[i]:.3e} > {tol}")
+
+
+def check_records(dump, p, opt_type, n_steps, seed, first, count, prec, scheme, fixings, bumps,
+                  za=None, zb=None, threads=8):
+    tol = TOL[prec]
+    mode = oracle.ABSORB if scheme == 1 else oracle.FULL_TRUNC
+    rec = oracle.simulate(p, opt_type, n_steps, seed, first, count, mode, fixings, za, zb, threads)
+    X = rec[:, 2]
+    near = np.abs(X - p.K) < 1e3 * tol * p.K
+    fl = floors(p)
+    for k, name in enumerate(oracle.REC_FIELDS):
+        compare(name, dump[:, k], rec[:, k], tol, fl[name],
+                allow=near if name in ("pw_delta", "pw_rho") else None)
+    compare("x_T", dump[:, 14], np.log(rec[:, 0] / p.S0), tol, 1.0)
+    if bumps:
+        pay, _ = oracle.scenario_payoffs(p, opt_type, n_steps, seed, count, first, mode, fixings,
+                                         za=za, zb=zb, threads=threads)
+        for k, sc in enumerate(oracle.SCENARIOS[1:]):
+            # payoffs are continuous in the average, so no indicator allowance
+            compare("pay_" + sc, dump[:, 6 + k], pay[sc], tol, p.S0)
+    else:
+        assert np.isnan(dump[:, 6:14]).all()
+    return rec
+
+
+def dump(hm, ctx, p, opt_type, n_paths, n_steps, seed, first, count, opts):
+    t = ctx.dump_paths(p.__dict__, opt_type, n_paths, n_steps, seed, first, count, opts)
+    return t.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+
+def test_european_fp64_bumps_full_parity(hm, ctx):
+    """European call, 1e4 paths x 100 steps, FP64, bumps on common random
+    numbers: every path, every scenario."""
+    n, N, seed = 10_000, 100, 42
+    opts = hm.Options()
+    d = dump(hm, ctx, PB, hm.EURO_CALL, n, N, seed, 0, n, opts)
+    check_records(d, PB, oracle.EURO_CALL, N, seed, 0, n, 0, 0, None, True)
+    r = ctx.price_greeks(PB.__dict__, hm.EURO_CALL, n, N, seed, opts)
+    ref = oracle.price_greeks(PB, oracle.EURO_CALL, n, N, seed, threads=8)
+    for k, (v, se) in ref.items():
+        assert r[k][0] == pytest.approx(v, rel=1e-10, abs=1e-12), k
+        assert r[k][1] == pytest.approx(se, rel=1e-6), k
+
+
+@pytest.mark.parametrize("opt_type", [0, 1, 2, 3])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_fp64_all_types_ragged(hm, ctx, opt_type, scheme):
+    n, N, seed = 1000 + 37, 7, 0xDEADBEEF12345
+    fix = (2, 3, 7) if opt_type >= 2 else None
+    p = PP if scheme == 1 else PB
+    opts = hm.Options(scheme=scheme, fixings=fix)
+    d = dump(hm, ctx, p, opt_type, n, N, seed, 0, n, opts)
+    check_records(d, p, opt_type, N, seed, 0, n, 0, scheme, fix, True)
+
+
+@pytest.mark.parametrize("opt_type", [0, 1, 2, 3])
+def test_fp32_all_types(hm, ctx, opt_type):
+    n, N, seed = 4096 + 100, 63, 7
+    opts = hm.Options(precision=hm.FP32)
+    d = dump(hm, ctx, PB, opt_type, n, N, seed, 0, n, opts)
+    check_records(d, PB, opt_type, N, seed, 0, n, 1, 0, None, True)
+
+
+def test_asian_fp32_daily_fixings_252_steps(hm, ctx):
+    n, N, seed = 1 << 14, 252, 42
+    opts = hm.Options(precision=hm.FP32)
+    d = dump(hm, ctx, PB, hm.ASIAN_CALL, n, N, seed, 0, n, opts)
+    check_records(d, PB, oracle.ASIAN_CALL, N, seed, 0, n, 1, 0, None, True)
+
+
+def test_paper_quarterly_asian_absorption(hm, ctx):
+    N = 128
+    fix = paper_fixing_steps(N)
+    opts = hm.Options(scheme=hm.ABSORPTION, fixings=fix)
+    d = dump(hm, ctx, PP, hm.ASIAN_CALL, 3000, N, 1, 0, 3000, opts)
+    check_records(d, PP, oracle.ASIAN_CALL, N, 1, 0, 3000, 0, 1, fix, True)
+
+
+def test_asian_fp32_large_sampled_and_reduction(hm, ctx):
+    """The 2^20-path x 252-step FP32 Asian call with five bump Greeks, in the
+    launch the benchmark times: sampled paths against the oracle, and the
+    reduced estimates against the host sum of every path's record."""
+    n, N, seed = 1 << 20, 252, 42
+    opts = hm.Options(precision=hm.FP32)
+    r = ctx.price_greeks(PB.__dict__, hm.ASIAN_CALL, n, N, seed, opts)
+    full = dump(hm, ctx, PB, hm.ASIAN_CALL, n, N, seed, 0, n, opts)
+    for first in (0, n // 2 + 12345, n - 700):
+        check_records(full[first:first + 700], PB, oracle.ASIAN_CALL, N, seed, first, 700, 1, 0,
+                      None, True)
+    pay = {sc: full[:, 6 + k] for k, sc in enumerate(oracle.SCENARIOS[1:])}
+    pay["base"] = full[:, 3]
+    samples = oracle.greek_samples(pay, PB)
+    samples["pw_delta"], samples["pw_rho"] = full[:, 4], full[:, 5]
+    for k, y in samples.items():
+        m, se = oracle.mean_se(y)
+        assert r[k][0] == pytest.approx(m, rel=1e-9, abs=1e-12), k
+        assert r[k][1] == pytest.approx(se, rel=1e-6), k
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("N", [1, 5, 64])
+def test_sobol_bridge_parity(hm, ctx, prec, N):
+    from oracle import sobol
+    R, M, seed = 4, 700, 42
+    n = R * M
+    opts = hm.Options(precision=prec, rng=hm.SOBOL_BRIDGE, qmc_replicates=R)
+    d = dump(hm, ctx, PB, hm.ASIAN_CALL, n, N, seed, 0, n, opts)
+    za, zb = sobol.normals(N, 0, n, R, M, seed)
+    check_records(d, PB, oracle.ASIAN_CALL, N, seed, 0, n, prec, 0, None, True, za, zb)
+    r = ctx.price_greeks(PB.__dict__, hm.ASIAN_CALL, n, N, seed, opts)
+    means = d[:, 3].reshape(R, M).mean(axis=1)
+    assert r["price"][0] == pytest.approx(means.mean(), rel=1e-12)
+    assert r["price"][1] == pytest.approx(means.std(ddof=1) / math.sqrt(R), rel=1e-9)
+
+
+def test_sobol_bridge_full_size_sampled(hm, ctx):
+    from oracle import sobol
+    R, M, N, seed = 16, 1 << 16, 252, 42
+    n = R * M
+    opts = hm.Options(precision=hm.FP32, rng=hm.SOBOL_BRIDGE, qmc_replicates=R)
+    for first in (0, 5 * M - 300, n - 500):
+        d = dump(hm, ctx, PB, hm.ASIAN_CALL, n, N, seed, first, 500, opts)
+        za, zb = sobol.normals(N, first, 500, R, M, seed)
+        check_records(d, PB, oracle.ASIAN_CALL, N, seed, first, 500, 1, 0, None, True, za, zb)
+
+
+def test_path_index_above_2_32_and_wide_seed(hm, ctx):
+    first, count, N, seed = (1 << 32) + 5, 300, 9, (7 << 40) | 3
+    opts = hm.Options()
+    d = dump(hm, ctx, PB, hm.EURO_PUT, first + count, N, seed, first, count, opts)
+    check_records(d, PB, oracle.EURO_PUT, N, seed, first, count, 0, 0, None, True)
+
+
+def test_minimum_paths_and_one_step(hm, ctx):
+    r = ctx.price_greeks(PB.__dict__, hm.EURO_CALL, 2, 1, 3, hm.Options())
+    rec = oracle.simulate(PB, oracle.EURO_CALL, 1, 3, 0, 2)
+    m, se = oracle.mean_se(rec[:, 3])
+    assert r["price"][0] == pytest.approx(m, rel=1e-12, abs=1e-13)
+    assert r["price"][1] == pytest.approx(se, rel=1e-9, abs=1e-13)
+
+
+def test_default_entry_point_matches_ex(hm, ctx):
+    a = hm.price_greeks(PB.__dict__, hm.EURO_CALL, 10_000, 100, 42)
+    b = ctx.price_greeks(PB.__dict__, hm.EURO_CALL, 10_000, 100, 42, hm.Options())
+    for k in hm.EST_NAMES:
+        assert a[k] == b[k], k
+
+
+def test_bitwise_reproducible(hm, ctx):
+    opts = hm.Options(precision=hm.FP32)
+    a = ctx.price_greeks(PB.__dict__, hm.ASIAN_PUT, 100_000, 50, 9, opts)
+    b = ctx.price_greeks(PB.__dict__, hm.ASIAN_PUT, 100_000, 50, 9, opts)
+    for k in hm.EST_NAMES:
+        assert a[k] == b[k], k
+
+
+def test_statistics_against_analytic(hm, ctx):
+    """FP32, 2^20 paths x 100 steps: European call price and Greeks within
+    4 SE plus a discretisation allowance of the analytic Heston values."""
+    from oracle import analytic
+    g = analytic.heston_call_greeks(PB)
+    r = ctx.price_greeks(PB.__dict__, hm.EURO_CALL, 1 << 20, 100, 42,
+                         hm.Options(precision=hm.FP32))
+    bias = {"price": 0.01, "delta": 5e-4, "gamma": 2e-4, "vega": 0.2, "rho": 0.1, "theta": 0.05,
+            "pw_delta": 5e-4, "pw_rho": 0.1}
+    for k, b in bias.items():
+        ref = g[{"pw_delta": "delta", "pw_rho": "rho"}.get(k, k)]
+        assert abs(r[k][0] - ref) < 4 * r[k][1] + b, (k, r[k], ref)
+
+
+@pytest.mark.parametrize("bad", ["nan", "paths", "rho", "fix", "reps", "steps"])
+def test_invalid_arguments_are_rejected(hm, ctx, bad):
+    p = dict(BASE)
+    n, N, opts = 1000, 10, hm.Options()
+    if bad == "nan":
+        p["sigma"] = float("nan")
+    elif bad == "paths":
+        n = 1
+    elif bad == "rho":
+        p["rho"] = 1.5
+    elif bad == "fix":
+        opts = hm.Options(fixings=(3, 3, 5))
+        with pytest.raises(hm.HestonError) as e:
+            ctx.price_greeks(p, hm.ASIAN_CALL, n, N, 1, opts)
+        assert e.value.status == -1
+        return
+    elif bad == "reps":
+        opts = hm.Options(rng=hm.SOBOL_BRIDGE, qmc_replicates=3)
+    elif bad == "steps":
+        N = 0
+    with pytest.raises(hm.HestonError) as e:
+        ctx.price_greeks(p, hm.EURO_CALL, n, N, 1, opts)
+    assert e.value.status == -1
