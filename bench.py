@@ -40,6 +40,12 @@ OPS_PER_PATH_STEP = 122.0
 # (256 CUs x 128 lanes/clk x 2.4 GHz); every counted operation is priced as one
 # such lane-operation.
 ALU_PEAK_OPS = 256 * 128 * 2.4e9
+# HBM bytes per launch of the path kernel from the FETCH_SIZE / WRITE_SIZE
+# counter passes (FETCH_SIZE scaled by 2.00 and WRITE_SIZE by 1.00, the factors
+# a 256 MiB device copy reads under the same counters); see
+# profiles/price_kernel_asian_2p20x252_fp32_bumps_hbm_counters.md.  Set to None
+# whenever the kernel changes until the counters are taken again.
+TRAFFIC_BYTES_PER_LAUNCH = 712_000
 
 
 def parse():
@@ -49,6 +55,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--legs", default="qmc,adjoint",
+                    help="extra legs reported after the timed steps: qmc, adjoint, and copy "
+                         "(a 256 MiB device copy that calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -79,6 +88,59 @@ def cpu_baseline(target_s: float):
             "kind": "oracle",
             "sample": f"first {n} of {wl.n_paths} paths x {wl.n_steps} steps, 9 scenarios "
                       f"re-simulated in FP64 ({dt:.1f} s)"}
+
+
+ADJ_BUMPS = (("S0", 0, 1, 0.01), ("v0", 4, 1, 0.01), ("r", 2, 0, 1e-4), ("kappa", 5, 1, 0.01),
+             ("theta", 6, 1, 0.01), ("sigma", 7, 1, 0.01), ("rho", 8, 0, 0.01))
+
+
+def adjoint_vs_bump(ctx, hm, torch):
+    """European and Asian call, 2^22 paths x 365 steps, FP32: the seven
+    sensitivities by the adjoint (forward with checkpoints every 16 steps +
+    reverse sweep) against plain central bump-and-revalue (15 independent
+    revaluations on common random numbers).  speedup_at_equal_se =
+    (t_bump / t_adjoint) x (se_bump / se_adjoint)^2 per sensitivity."""
+    from workloads import ADJOINT_LARGE as A
+    n, N, seed = A["n_paths"], A["n_steps"], A["seed"]
+    every = A["checkpoint_every"]
+    opts = hm.Options(precision=hm.FP32, greeks=hm.GREEKS_PATHWISE)
+    ck = torch.empty(hm.ckpt_bytes(n, N, every, hm.FP32), dtype=torch.uint8, device="cuda:0")
+    out = {"n_paths": n, "n_steps": N, "checkpoint_every": every}
+    for name, typ in (("euro_call", hm.EURO_CALL), ("asian_call", hm.ASIAN_CALL)):
+        for _ in range(2):
+            ctx.adjoint_forward(A["params"], typ, n, N, seed, ck, every, opts)
+            ctx.adjoint_backward(A["params"], typ, n, N, seed, ck, every, 1.0, opts)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            price, fms = ctx.adjoint_forward(A["params"], typ, n, N, seed, ck, every, opts)
+            grads, bms = ctx.adjoint_backward(A["params"], typ, n, N, seed, ck, every, 1.0, opts)
+        torch.cuda.synchronize()
+        t_adj = (time.perf_counter() - t0) / reps
+        bumps = [(idx, rel, h) for _, idx, rel, h in ADJ_BUMPS]
+        ctx.bump_revalue(A["params"], typ, n, N, seed, bumps, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rb = ctx.bump_revalue(A["params"], typ, n, N, seed, bumps, opts)
+        torch.cuda.synchronize()
+        t_bump = time.perf_counter() - t0
+        per = {}
+        for k, (pname, _, _, _) in enumerate(ADJ_BUMPS):
+            ga, sa = grads[k]
+            gb, sb = rb["first"][k]
+            per[pname] = {"adjoint": [ga, sa], "bump": [gb, sb],
+                          "speedup_at_equal_se": (t_bump / t_adj) * (sb / sa) ** 2}
+        out[name] = {
+            "price": price, "adjoint_ms": t_adj * 1e3, "forward_kernel_ms": fms,
+            "backward_kernel_ms": bms, "bump_ms": t_bump * 1e3,
+            "bump_kernels_ms": rb["device_ms"],
+            "adjoint_path_steps_per_s": n * N / t_adj,
+            "bump_path_steps_per_s": n * N / t_bump,
+            "speedup": t_bump / t_adj,
+            "min_speedup_at_equal_se": min(v["speedup_at_equal_se"] for v in per.values()),
+            "per_parameter": per}
+    return out
 
 
 def main():
@@ -118,23 +180,12 @@ def main():
     k_ms = float(np.mean(kernel_ms))
     achieved = OPS_PER_PATH_STEP * path_steps / (k_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-                "unit": "Top/s", "frac": achieved / ALU_PEAK_OPS, "traffic": None,
+                "unit": "Top/s", "frac": achieved / ALU_PEAK_OPS,
+                "traffic": TRAFFIC_BYTES_PER_LAUNCH,
                 "kernel": "price_kernel<float, Philox, Asian, fused bumps, full truncation>",
                 "kernel_ms": k_ms}
 
-    # the same step with Sobol + Brownian-bridge normals (16 shifted replicates)
-    qopts = hm.Options(precision=hm.FP32, rng=hm.SOBOL_BRIDGE, qmc_replicates=QMC_REPLICATES)
-    for _ in range(2):
-        ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, qopts)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    qk = []
-    for _ in range(5):
-        rq = ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, qopts)
-        qk.append(rq["device_ms"])
-    torch.cuda.synchronize()
-    q_ms = (time.perf_counter() - t1) / 5 * 1e3
-
+    legs = set(a for a in args.legs.split(",") if a)
     out = {
         "metric": METRIC, "value": value, "unit": "path-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -147,10 +198,31 @@ def main():
         "roofline": roofline,
         "estimates": {k: r[k] for k in ("price", "delta", "gamma", "vega", "rho", "theta",
                                         "pw_delta", "pw_rho")},
-        "qmc_sobol_bridge": {"value": path_steps / (q_ms * 1e-3), "unit": "path-steps/s",
-                             "ms_per_step": q_ms, "kernel_ms": float(np.mean(qk)),
-                             "price": rq["price"], "replicates": QMC_REPLICATES},
     }
+    if "qmc" in legs:
+        # the same step with Sobol + Brownian-bridge normals (16 shifted replicates)
+        qopts = hm.Options(precision=hm.FP32, rng=hm.SOBOL_BRIDGE, qmc_replicates=QMC_REPLICATES)
+        for _ in range(2):
+            ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, qopts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        qk = []
+        for _ in range(5):
+            rq = ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, qopts)
+            qk.append(rq["device_ms"])
+        torch.cuda.synchronize()
+        q_ms = (time.perf_counter() - t1) / 5 * 1e3
+        out["qmc_sobol_bridge"] = {"value": path_steps / (q_ms * 1e-3), "unit": "path-steps/s",
+                                   "ms_per_step": q_ms, "kernel_ms": float(np.mean(qk)),
+                                   "price": rq["price"], "replicates": QMC_REPLICATES}
+    if "adjoint" in legs:
+        out["adjoint_vs_bump"] = adjoint_vs_bump(ctx, hm, torch)
+    if "copy" in legs:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     ctx.close()

@@ -81,7 +81,8 @@ enum { HESTON_FULL_TRUNCATION = 0, HESTON_ABSORPTION = 1 };
 enum {
     HESTON_GREEKS_PATHWISE = 1u,   /* paper's pathwise Delta and Rho              */
     HESTON_GREEKS_BUMP_FUSED = 2u, /* 5 bump Greeks, one pass sharing the normals */
-    HESTON_GREEKS_BUMP_PLAIN = 4u  /* 5 bump Greeks, 9 independent revaluations   */
+    HESTON_GREEKS_BUMP_PLAIN = 4u  /* 5 bump Greeks, 9 independent revaluations
+                                      (exclusive with BUMP_FUSED)                */
 };
 
 /* valid_mask bits of heston_result. */
@@ -178,6 +179,70 @@ heston_status heston_dump_paths(heston_ctx *ctx, const heston_params *params,
                                 heston_option_type type, uint64_t n_paths, uint32_t n_steps,
                                 uint64_t seed, const heston_opts *opts, uint64_t first,
                                 uint64_t count, double *out_dev);
+
+/* ------------------------------------------------------------------------
+ * Plain bump-and-revalue on common random numbers.
+ *
+ * Every scenario is an independent revaluation (a full launch that regenerates
+ * the same Philox or Sobol normals): the base scenario, then for each bump b
+ * the up and the down revaluation of one input.  Returns the base price, the
+ * central first difference (P+ - P-) / (2h) and the second difference
+ * (P+ - 2P + P-) / h^2 of every bump, each with the standard error of its
+ * per-path difference.  A T bump keeps n_steps and the fixing step indices,
+ * so dt is rescaled.  Up to 8 bumps; the per-path payoffs of all 1 + 2 n_bumps
+ * scenarios are held on the device (8 bytes per path per scenario).  Errors:
+ * INVALID_ARGUMENT (bad bump, a bumped input out of range), the pricing
+ * call's errors. */
+typedef enum heston_param {
+    HESTON_P_S0 = 0, HESTON_P_K = 1, HESTON_P_R = 2, HESTON_P_T = 3, HESTON_P_V0 = 4,
+    HESTON_P_KAPPA = 5, HESTON_P_THETA = 6, HESTON_P_SIGMA = 7, HESTON_P_RHO = 8
+} heston_param;
+
+typedef struct heston_bump {
+    int32_t param;    /* heston_param                                        */
+    int32_t relative; /* nonzero: h = size * |input|; zero: h = size          */
+    double size;
+} heston_bump;
+
+#define HESTON_MAX_BUMPS 8
+heston_status heston_bump_revalue(heston_ctx *ctx, const heston_params *params,
+                                  heston_option_type type, uint64_t n_paths, uint32_t n_steps,
+                                  uint64_t seed, const heston_opts *opts,
+                                  const heston_bump *bumps, uint32_t n_bumps,
+                                  heston_est *price, heston_est *first, heston_est *second,
+                                  double *device_ms);
+
+/* ------------------------------------------------------------------------
+ * Adjoint (reverse-mode) sensitivities of the price to
+ * theta = (S0, v0, r, kappa, theta, sigma, rho): the exact derivative of every
+ * path's discounted payoff (pathwise method, section "Pathwise method for
+ * greeks estimation", carried through every Milstein step), averaged over
+ * paths.  Philox normals only; |rho| < 1.
+ *
+ * heston_adjoint_forward prices the option and writes the step states every
+ * `every` steps (8 or 16) and the final state into the caller-owned DEVICE
+ * buffer ckpt_dev of at least heston_adjoint_ckpt_bytes(...) bytes.
+ * heston_adjoint_backward, called with the same request and the unchanged
+ * buffer, recomputes each segment from its checkpoint with the same normals
+ * and runs the reverse sweep; grads[k] = dprice * mean over paths of the
+ * derivative, with its standard error.  per_path_dev (nullable, DEVICE,
+ * [n_paths][8] doubles) receives each path's payoff and its seven derivatives
+ * times dprice.  The buffer layout is private to the library.  Errors:
+ * INVALID_ARGUMENT (bad request, every not 8 or 16, buffer too small),
+ * UNSUPPORTED (Sobol normals, bump Greeks in opts are ignored), DEVICE_ERROR. */
+uint64_t heston_adjoint_ckpt_bytes(uint64_t n_paths, uint32_t n_steps, uint32_t every,
+                                   int32_t precision);
+heston_status heston_adjoint_forward(heston_ctx *ctx, const heston_params *params,
+                                     heston_option_type type, uint64_t n_paths, uint32_t n_steps,
+                                     uint64_t seed, const heston_opts *opts, uint32_t every,
+                                     void *ckpt_dev, uint64_t ckpt_bytes, heston_est *price,
+                                     double *device_ms);
+heston_status heston_adjoint_backward(heston_ctx *ctx, const heston_params *params,
+                                      heston_option_type type, uint64_t n_paths,
+                                      uint32_t n_steps, uint64_t seed, const heston_opts *opts,
+                                      uint32_t every, const void *ckpt_dev, uint64_t ckpt_bytes,
+                                      double dprice, heston_est grads[7], double *per_path_dev,
+                                      double *device_ms);
 
 /* Static description of a status code; never NULL. */
 const char *heston_status_str(heston_status status);

@@ -33,7 +33,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT = 0, 1, 2, 3
 FULL_TRUNC, ABSORB = 0, 1
 REC_FIELDS = ("S_T", "V_T", "Sbar", "pay", "pw_delta", "pw_rho")
-TAN_FIELDS = ("pay", "d_S0", "d_v0", "d_r", "d_kappa", "d_theta", "d_sigma", "d_rho")
+TAN_FIELDS = ("pay", "d_S0", "d_v0", "d_r", "d_kappa", "d_theta", "d_sigma", "d_rho",
+              "max_dsqrt")
 PARAM_NAMES = ("S0", "K", "r", "T", "v0", "kappa", "theta", "sigma", "rho")
 
 
@@ -138,7 +139,8 @@ def simulate(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int =
 def tangent(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int = 0,
             n_paths: int = 1, mode: int = FULL_TRUNC, fixings=None, za=None, zb=None,
             threads: int = 1) -> np.ndarray:
-    """Per-path [n_paths, 8] = (pay, d/dS0, d/dv0, d/dr, d/dkappa, d/dtheta, d/dsigma, d/drho)."""
+    """Per-path [n_paths, 9] = (pay, d/dS0, d/dv0, d/dr, d/dkappa, d/dtheta, d/dsigma, d/drho,
+    max_j sqrt(dt / V+_j) / 2), the last the largest factor d sqrt(V+ dt)/dV+ on the path."""
     return _run("or_tangent", len(TAN_FIELDS), p, opt_type, n_steps, seed, first, n_paths, mode,
                 fixings, za, zb, threads)
 

@@ -44,7 +44,8 @@
 #include <string.h>
 
 #define OR_REC 6    /* S_T, V_T, Sbar, discounted payoff, pathwise Delta, pathwise Rho */
-#define OR_TAN 8    /* discounted payoff, d/dS0, d/dv0, d/dr, d/dkappa, d/dtheta, d/dsigma, d/drho */
+#define OR_TAN 9    /* discounted payoff, d/dS0, d/dv0, d/dr, d/dkappa, d/dtheta, d/dsigma, d/drho,
+                       then the path's largest d sqrt(V+ dt) / dV+ = max_j sqrt(dt / V+_j) / 2 */
 
 typedef struct {
     double S0, K, r, T, v0, kappa, theta, sigma, rho;
@@ -203,6 +204,7 @@ static void tan_path(const or_params *P, int type, uint32_t N, const uint8_t *fi
     double S = P->S0, dS[NP] = { 0 };
     double V = P->v0, dV[NP] = { 0 };
     double A = 0.0, dA[NP] = { 0 };
+    double amp = 0.0;
     dS[I_S0] = 1.0;
     dV[I_V0] = 1.0;
     for (uint32_t j = 0; j < N; ++j) {
@@ -220,6 +222,8 @@ static void tan_path(const or_params *P, int type, uint32_t N, const uint8_t *fi
             dvp[k] = pos ? dV[k] : 0.0;
         double sq = sqrt(vp * dt);                  /* sqrt(V+ dt)          */
         double dsq_dvp = pos ? dt / (2.0 * sq) : 0.0; /* d sqrt(V+ dt)/d V+   */
+        if (dsq_dvp > amp)
+            amp = dsq_dvp;
 
         /* log-price increment and its derivatives */
         double inc = (P->r - 0.5 * vp) * dt + sq * z1;
@@ -280,6 +284,7 @@ static void tan_path(const or_params *P, int type, uint32_t N, const uint8_t *fi
     for (int k = 0; k < NP; ++k)
         out[1 + k] = itm ? D * sgn * dX[k] : 0.0;
     out[1 + I_R] += -P->T * pay; /* the discount factor depends on r */
+    out[1 + NP] = amp;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -64,11 +64,15 @@ class COpts(ctypes.Structure):
         ("bump_r_abs", ctypes.c_double), ("bump_T_abs", ctypes.c_double)]
 
 
+class CBump(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_int32), ("relative", ctypes.c_int32), ("size", ctypes.c_double)]
+
+
 _lib = None
 
-EXPORTS = ("heston_default_opts", "heston_ctx_create", "heston_ctx_destroy",
-           "heston_price_greeks_ex", "heston_price_greeks", "heston_dump_paths",
-           "heston_status_str", "heston_last_error", "heston_abi_version")
+# heston_param indices
+P_S0, P_K, P_R, P_T, P_V0, P_KAPPA, P_THETA, P_SIGMA, P_RHO = range(9)
+ADJOINT_PARAMS = ("S0", "v0", "r", "kappa", "theta", "sigma", "rho")
 
 
 def lib():
@@ -94,6 +98,18 @@ def lib():
     L.heston_last_error.argtypes = []
     L.heston_last_error.restype = c.c_char_p
     L.heston_abi_version.restype = c.c_int
+    L.heston_bump_revalue.argtypes = [c.c_void_p, P(CParams), c.c_int, c.c_uint64, c.c_uint32,
+                                      c.c_uint64, P(COpts), P(CBump), c.c_uint32, P(CEst),
+                                      P(CEst), P(CEst), P(c.c_double)]
+    L.heston_adjoint_ckpt_bytes.argtypes = [c.c_uint64, c.c_uint32, c.c_uint32, c.c_int32]
+    L.heston_adjoint_ckpt_bytes.restype = c.c_uint64
+    L.heston_adjoint_forward.argtypes = [c.c_void_p, P(CParams), c.c_int, c.c_uint64, c.c_uint32,
+                                         c.c_uint64, P(COpts), c.c_uint32, c.c_void_p,
+                                         c.c_uint64, P(CEst), P(c.c_double)]
+    L.heston_adjoint_backward.argtypes = [c.c_void_p, P(CParams), c.c_int, c.c_uint64,
+                                          c.c_uint32, c.c_uint64, P(COpts), c.c_uint32,
+                                          c.c_void_p, c.c_uint64, c.c_double, P(CEst),
+                                          c.c_void_p, P(c.c_double)]
     _lib = L
     return L
 
@@ -214,6 +230,59 @@ class Context:
                                       seed, ctypes.byref(o.c), first, count,
                                       ctypes.c_void_p(out.data_ptr())))
         return out
+
+
+    def bump_revalue(self, params, opt_type: int, n_paths: int, n_steps: int, seed: int,
+                     bumps, opts: Options | None = None) -> dict:
+        """Plain bump-and-revalue: bumps = [(param index, relative, size)].
+        Returns {'price': (v, se), 'first': [(v, se)], 'second': [(v, se)], 'device_ms'}."""
+        o = _OptsHolder(opts or Options(), n_steps)
+        cb = (CBump * len(bumps))(*[CBump(int(a), int(r), float(h)) for a, r, h in bumps])
+        price = CEst()
+        first = (CEst * len(bumps))()
+        second = (CEst * len(bumps))()
+        ms = ctypes.c_double()
+        cp = _cparams(params)
+        check(lib().heston_bump_revalue(self.handle, ctypes.byref(cp), opt_type, n_paths, n_steps,
+                                        seed, ctypes.byref(o.c), cb, len(bumps),
+                                        ctypes.byref(price), first, second, ctypes.byref(ms)))
+        return {"price": (price.value, price.std_err),
+                "first": [(e.value, e.std_err) for e in first],
+                "second": [(e.value, e.std_err) for e in second], "device_ms": ms.value}
+
+    def adjoint_forward(self, params, opt_type: int, n_paths: int, n_steps: int, seed: int,
+                        ckpt, every: int = 16, opts: Options | None = None):
+        """Prices and fills the checkpoint tensor (uint8, on the device)."""
+        o = _OptsHolder(opts or Options(greeks=GREEKS_PATHWISE), n_steps)
+        price, ms = CEst(), ctypes.c_double()
+        cp = _cparams(params)
+        check(lib().heston_adjoint_forward(self.handle, ctypes.byref(cp), opt_type, n_paths,
+                                           n_steps, seed, ctypes.byref(o.c), every,
+                                           ctypes.c_void_p(ckpt.data_ptr()),
+                                           ckpt.numel() * ckpt.element_size(),
+                                           ctypes.byref(price), ctypes.byref(ms)))
+        return (price.value, price.std_err), ms.value
+
+    def adjoint_backward(self, params, opt_type: int, n_paths: int, n_steps: int, seed: int,
+                         ckpt, every: int = 16, dprice: float = 1.0,
+                         opts: Options | None = None, per_path=None):
+        """[(value, se)] for d price / d (S0, v0, r, kappa, theta, sigma, rho), times dprice."""
+        o = _OptsHolder(opts or Options(greeks=GREEKS_PATHWISE), n_steps)
+        grads, ms = (CEst * 7)(), ctypes.c_double()
+        cp = _cparams(params)
+        pp = ctypes.c_void_p(per_path.data_ptr()) if per_path is not None else None
+        if per_path is not None:
+            assert per_path.is_contiguous() and per_path.numel() >= 8 * n_paths
+        check(lib().heston_adjoint_backward(self.handle, ctypes.byref(cp), opt_type, n_paths,
+                                            n_steps, seed, ctypes.byref(o.c), every,
+                                            ctypes.c_void_p(ckpt.data_ptr()),
+                                            ckpt.numel() * ckpt.element_size(), float(dprice),
+                                            grads, pp, ctypes.byref(ms)))
+        return [(g.value, g.std_err) for g in grads], ms.value
+
+
+def ckpt_bytes(n_paths: int, n_steps: int, every: int = 16, precision: int = FP32) -> int:
+    return int(lib().heston_adjoint_ckpt_bytes(n_paths, n_steps, every, precision))
 
 
 def _result_dict(res: CResult) -> dict:

@@ -9,8 +9,10 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("api.hip", "price_kernel.hip")]
-HDRS = [os.path.join(HERE, "csrc", f) for f in ("internal.hpp", "device_math.hpp")] + \
+SRC = [os.path.join(HERE, "csrc", f) for f in ("api.hip", "price_kernel.hip",
+                                               "adjoint_kernel.hip")]
+HDRS = [os.path.join(HERE, "csrc", f) for f in ("internal.hpp", "device_math.hpp",
+                                                "path_step.hpp")] + \
     [os.path.join(os.path.dirname(HERE), "include", "heston.h")]
 LIB = os.path.join(HERE, "libheston.so")
 ARCH = os.environ.get("HESTON_OFFLOAD_ARCH", "gfx950")

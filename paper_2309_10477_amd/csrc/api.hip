@@ -47,6 +47,7 @@ struct heston_ctx {
     uint64_t budget = 0;  // 0 = unlimited
     uint64_t in_use = 0;  // bytes held by the buffers below
     DevBuf partials, rep_sums, fix_bits, sobol_dirs, sobol_shift, bridge_start, bridge_ops;
+    DevBuf pay, bump_partials, bump_sums;
     double *host_sums = nullptr; // pinned
     size_t host_sums_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -225,9 +226,11 @@ heston_status check_request(const Request &q)
         return fail(HESTON_INVALID_ARGUMENT, "unknown scheme");
     if (o.greeks & ~7u)
         return fail(HESTON_INVALID_ARGUMENT, "unknown greeks bits");
-    if (o.greeks & HESTON_GREEKS_BUMP_PLAIN)
-        return fail(HESTON_UNSUPPORTED, "BUMP_PLAIN is served by heston_price_greeks_plain");
-    if (o.greeks & HESTON_GREEKS_BUMP_FUSED) {
+    if ((o.greeks & HESTON_GREEKS_BUMP_PLAIN) && (o.greeks & HESTON_GREEKS_BUMP_FUSED))
+        return fail(HESTON_INVALID_ARGUMENT, "BUMP_PLAIN and BUMP_FUSED are exclusive");
+    if ((o.greeks & HESTON_GREEKS_BUMP_PLAIN) && o.rng != HESTON_RNG_PHILOX)
+        return fail(HESTON_UNSUPPORTED, "plain bump-and-revalue needs Philox normals");
+    if (o.greeks & (HESTON_GREEKS_BUMP_FUSED | HESTON_GREEKS_BUMP_PLAIN)) {
         const double b[] = {o.bump_S0_rel, o.bump_v0_rel, o.bump_r_abs, o.bump_T_abs};
         for (double x : b)
             if (!std::isfinite(x) || !(x > 0))
@@ -422,6 +425,115 @@ heston_ctx *default_ctx(heston_status &st)
     return per_device[dev];
 }
 
+double &param_ref(heston_params &p, int k)
+{
+    double *f[] = {&p.S0, &p.K, &p.r, &p.T, &p.v0, &p.kappa, &p.theta, &p.sigma, &p.rho};
+    return *f[k];
+}
+
+// Plain bump-and-revalue: 1 + 2 nb independent launches writing per-path
+// payoffs, then per-path differences reduced on the device.  base_sums
+// (nullable, host N_ACC doubles) receives the base launch's estimator sums.
+heston_status bump_revalue_impl(heston_ctx *c, const Request &q0, const heston_bump *bumps,
+                                uint32_t nb, heston_est *price, heston_est *first,
+                                heston_est *second, double *device_ms, double *base_sums)
+{
+    if (nb < 1 || nb > (uint32_t)MAX_BUMPS || !bumps)
+        return fail(HESTON_INVALID_ARGUMENT, "need 1..8 bumps");
+    if (q0.o.rng != HESTON_RNG_PHILOX)
+        return fail(HESTON_UNSUPPORTED, "plain bump-and-revalue needs Philox normals");
+    const uint64_t n = q0.n_paths;
+    std::vector<Request> qs(1 + 2 * nb, q0);
+    BumpScales sc;
+    std::memset(&sc, 0, sizeof(sc));
+    for (auto &q : qs)
+        q.o.greeks = HESTON_GREEKS_PATHWISE;
+    for (uint32_t b = 0; b < nb; ++b) {
+        const heston_bump &bp = bumps[b];
+        if (bp.param < 0 || bp.param > 8 || !std::isfinite(bp.size) || !(bp.size > 0))
+            return fail(HESTON_INVALID_ARGUMENT, "bump " + std::to_string(b) + " is invalid");
+        heston_params base = q0.p;
+        const double h = bp.relative ? bp.size * std::fabs(param_ref(base, bp.param)) : bp.size;
+        if (!(h > 0))
+            return fail(HESTON_INVALID_ARGUMENT, "bump " + std::to_string(b) + " has size 0");
+        param_ref(qs[1 + 2 * b].p, bp.param) += h;
+        param_ref(qs[2 + 2 * b].p, bp.param) -= h;
+        sc.first[b] = 1.0 / (2.0 * h);
+        sc.second[b] = 1.0 / (h * h);
+        for (int k = 1; k <= 2; ++k) {
+            heston_status st = check_request(qs[k + 2 * b]);
+            if (st != HESTON_OK)
+                return fail(st, "bumped scenario " + std::to_string(b) + ": " + g_last_error);
+        }
+    }
+    heston_status st;
+    const size_t rows = qs.size();
+    if ((st = reserve(c, c->pay, rows * n * 8)) != HESTON_OK)
+        return st;
+    double *pay = (double *)c->pay.ptr;
+    HIP_TRY(hipEventRecord(c->ev0, c->stream));
+    PriceLaunch L;
+    for (size_t s = 0; s < rows; ++s) {
+        if ((st = plan(c, qs[s], 0, n, L)) != HESTON_OK)
+            return st;
+        L.pay_out = pay + s * n;
+        HIP_TRY(launch_paths(L, c->stream));
+        if (s == 0 && base_sums) {
+            HIP_TRY(launch_reduce(L, (double *)c->rep_sums.ptr, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->host_sums, c->rep_sums.ptr, N_ACC * 8, hipMemcpyDeviceToHost,
+                                   c->stream));
+        }
+    }
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, 2048);
+    if ((st = reserve(c, c->bump_partials, (size_t)blocks * BUMP_W * 8)) != HESTON_OK ||
+        (st = reserve(c, c->bump_sums, BUMP_W * 8)) != HESTON_OK)
+        return st;
+    HIP_TRY(launch_bump_combine(pay, n, nb, sc, (double *)c->bump_partials.ptr, blocks, c->stream));
+    HIP_TRY(hipEventRecord(c->ev1, c->stream));
+    HIP_TRY(launch_reduce_rows((double *)c->bump_partials.ptr, blocks, BUMP_W,
+                               (double *)c->bump_sums.ptr, c->stream));
+    double sums[BUMP_W];
+    HIP_TRY(hipMemcpyAsync(sums, c->bump_sums.ptr, sizeof(sums), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (base_sums)
+        std::memcpy(base_sums, c->host_sums, N_ACC * 8);
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    const double dn = (double)n;
+    if (price)
+        *price = est_from(dn, sums[0], sums[1]);
+    for (uint32_t b = 0; b < nb; ++b) {
+        if (first)
+            first[b] = est_from(dn, sums[2 + 4 * b], sums[3 + 4 * b]);
+        if (second)
+            second[b] = est_from(dn, sums[4 + 4 * b], sums[5 + 4 * b]);
+    }
+    if (device_ms)
+        *device_ms = ms;
+    return HESTON_OK;
+}
+
+heston_status check_adjoint(const Request &q, uint32_t every, const void *ckpt, uint64_t bytes)
+{
+    heston_status st = check_request(q);
+    if (st != HESTON_OK)
+        return st;
+    if (q.o.rng != HESTON_RNG_PHILOX)
+        return fail(HESTON_UNSUPPORTED, "adjoint sensitivities need Philox normals");
+    if (!(std::fabs(q.p.rho) < 1))
+        return fail(HESTON_INVALID_ARGUMENT, "adjoint needs |rho| < 1");
+    if (every != 8 && every != 16)
+        return fail(HESTON_INVALID_ARGUMENT, "checkpoint interval must be 8 or 16");
+    if (!ckpt)
+        return fail(HESTON_INVALID_ARGUMENT, "checkpoint buffer is NULL");
+    const uint64_t need =
+        ckpt_bytes(q.n_paths, q.n_steps, every, q.o.precision == HESTON_FP64 ? 8 : 4);
+    if (bytes < need)
+        return fail(HESTON_INVALID_ARGUMENT, "checkpoint buffer smaller than " +
+                                                 std::to_string(need) + " bytes");
+    return HESTON_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -474,7 +586,8 @@ heston_status heston_ctx_destroy(heston_ctx *c)
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift,
-                      &c->bridge_start, &c->bridge_ops})
+                      &c->bridge_start, &c->bridge_ops, &c->pay, &c->bump_partials,
+                      &c->bump_sums})
         if (b->ptr)
             (void)hipFree(b->ptr);
     if (c->host_sums)
@@ -498,6 +611,32 @@ heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
     if (st != HESTON_OK)
         return st;
     DeviceGuard g(c->device);
+    if (q.o.greeks & HESTON_GREEKS_BUMP_PLAIN) {
+        // five Greeks from four central bumps, each scenario revalued on its own
+        const heston_bump bumps[4] = {{HESTON_P_S0, 1, q.o.bump_S0_rel},
+                                      {HESTON_P_V0, 1, q.o.bump_v0_rel},
+                                      {HESTON_P_R, 0, q.o.bump_r_abs},
+                                      {HESTON_P_T, 0, q.o.bump_T_abs}};
+        heston_est price, first[4], second[4];
+        double sums[N_ACC], ms = 0;
+        if ((st = bump_revalue_impl(c, q, bumps, 4, &price, first, second, &ms, sums)) != HESTON_OK)
+            return st;
+        heston_result r;
+        std::memset(&r, 0, sizeof(r));
+        r.price = est_from((double)n_paths, sums[0], sums[1]);
+        r.pw_delta = est_from((double)n_paths, sums[2], sums[3]);
+        r.pw_rho = est_from((double)n_paths, sums[4], sums[5]);
+        r.delta = first[0];
+        r.gamma = second[0];
+        r.vega = first[1];
+        r.rho = first[2];
+        r.theta = heston_est{-first[3].value, first[3].std_err};
+        r.n_paths = n_paths;
+        r.valid_mask = HESTON_VALID_PRICE | HESTON_VALID_PATHWISE | HESTON_VALID_BUMPS;
+        r.device_ms = ms;
+        *out = r;
+        return HESTON_OK;
+    }
     PriceLaunch L;
     if ((st = plan(c, q, 0, n_paths, L)) != HESTON_OK)
         return st;
@@ -567,6 +706,109 @@ heston_status heston_dump_paths(heston_ctx *c, const heston_params *params,
     HIP_TRY(launch_paths(L, c->stream));
     HIP_TRY(launch_reduce(L, (double *)c->rep_sums.ptr, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    return HESTON_OK;
+}
+
+heston_status heston_bump_revalue(heston_ctx *c, const heston_params *params,
+                                  heston_option_type type, uint64_t n_paths, uint32_t n_steps,
+                                  uint64_t seed, const heston_opts *opts,
+                                  const heston_bump *bumps, uint32_t n_bumps, heston_est *price,
+                                  heston_est *first, heston_est *second, double *device_ms)
+{
+    if (!c)
+        return fail(HESTON_INVALID_ARGUMENT, "ctx is NULL");
+    if (opts && opts->struct_size != sizeof(heston_opts))
+        return fail(HESTON_INVALID_ARGUMENT, "opts->struct_size does not match this library");
+    Request q = make_request(params, type, n_paths, n_steps, seed, opts);
+    q.o.greeks = HESTON_GREEKS_PATHWISE;
+    heston_status st = check_request(q);
+    if (st != HESTON_OK)
+        return st;
+    DeviceGuard g(c->device);
+    return bump_revalue_impl(c, q, bumps, n_bumps, price, first, second, device_ms, nullptr);
+}
+
+uint64_t heston_adjoint_ckpt_bytes(uint64_t n_paths, uint32_t n_steps, uint32_t every,
+                                   int32_t precision)
+{
+    if (every == 0 || n_steps == 0 || (precision != HESTON_FP64 && precision != HESTON_FP32))
+        return 0;
+    return ckpt_bytes(n_paths, n_steps, every, precision == HESTON_FP64 ? 8 : 4);
+}
+
+heston_status heston_adjoint_forward(heston_ctx *c, const heston_params *params,
+                                     heston_option_type type, uint64_t n_paths, uint32_t n_steps,
+                                     uint64_t seed, const heston_opts *opts, uint32_t every,
+                                     void *ckpt_dev, uint64_t ckpt_nbytes, heston_est *price,
+                                     double *device_ms)
+{
+    if (!c || !price)
+        return fail(HESTON_INVALID_ARGUMENT, "ctx or price is NULL");
+    if (opts && opts->struct_size != sizeof(heston_opts))
+        return fail(HESTON_INVALID_ARGUMENT, "opts->struct_size does not match this library");
+    Request q = make_request(params, type, n_paths, n_steps, seed, opts);
+    q.o.greeks = HESTON_GREEKS_PATHWISE;
+    heston_status st = check_adjoint(q, every, ckpt_dev, ckpt_nbytes);
+    if (st != HESTON_OK)
+        return st;
+    DeviceGuard g(c->device);
+    PriceLaunch L;
+    if ((st = plan(c, q, 0, n_paths, L)) != HESTON_OK)
+        return st;
+    L.ckpt = ckpt_dev;
+    L.ckpt_every = every;
+    HIP_TRY(hipEventRecord(c->ev0, c->stream));
+    HIP_TRY(launch_paths(L, c->stream));
+    HIP_TRY(hipEventRecord(c->ev1, c->stream));
+    HIP_TRY(launch_reduce(L, (double *)c->rep_sums.ptr, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->host_sums, c->rep_sums.ptr, N_ACC * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    *price = est_from((double)n_paths, c->host_sums[0], c->host_sums[1]);
+    if (device_ms)
+        *device_ms = ms;
+    return HESTON_OK;
+}
+
+heston_status heston_adjoint_backward(heston_ctx *c, const heston_params *params,
+                                      heston_option_type type, uint64_t n_paths,
+                                      uint32_t n_steps, uint64_t seed, const heston_opts *opts,
+                                      uint32_t every, const void *ckpt_dev, uint64_t ckpt_nbytes,
+                                      double dprice, heston_est grads[7], double *per_path_dev,
+                                      double *device_ms)
+{
+    if (!c || !grads)
+        return fail(HESTON_INVALID_ARGUMENT, "ctx or grads is NULL");
+    if (opts && opts->struct_size != sizeof(heston_opts))
+        return fail(HESTON_INVALID_ARGUMENT, "opts->struct_size does not match this library");
+    if (!std::isfinite(dprice))
+        return fail(HESTON_INVALID_ARGUMENT, "dprice is not finite");
+    Request q = make_request(params, type, n_paths, n_steps, seed, opts);
+    q.o.greeks = HESTON_GREEKS_PATHWISE;
+    heston_status st = check_adjoint(q, every, ckpt_dev, ckpt_nbytes);
+    if (st != HESTON_OK)
+        return st;
+    DeviceGuard g(c->device);
+    PriceLaunch L;
+    if ((st = plan(c, q, 0, n_paths, L)) != HESTON_OK)
+        return st;
+    L.ckpt = const_cast<void *>(ckpt_dev);
+    L.ckpt_every = every;
+    HIP_TRY(hipEventRecord(c->ev0, c->stream));
+    HIP_TRY(launch_adjoint(L, dprice, per_path_dev, c->stream));
+    HIP_TRY(hipEventRecord(c->ev1, c->stream));
+    HIP_TRY(launch_reduce(L, (double *)c->rep_sums.ptr, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->host_sums, c->rep_sums.ptr, N_ACC * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    for (int k = 0; k < 7; ++k)
+        grads[k] = est_from((double)n_paths, c->host_sums[2 * (k + 1)], c->host_sums[2 * (k + 1) + 1]);
+    if (device_ms)
+        *device_ms = ms;
     return HESTON_OK;
 }
 

@@ -68,7 +68,52 @@ struct PriceLaunch {
     double *partials;               // device [n_reps][blocks_per_rep][N_ACC]
     uint32_t blocks_per_rep;
     double *dump;                   // device [n_paths][DUMP_WIDTH] or null
+    double *pay_out;                // device [n_paths] discounted payoff per path, or null
+    void *ckpt;                     // device checkpoint buffer (adjoint forward) or null
+    uint32_t ckpt_every;            // steps between checkpoints
 };
+
+// Checkpoint buffer of the adjoint, structure of arrays in the path state's
+// precision R: for c = 0 .. n_ckpt-1 the state at step c*every, x then V, each
+// [n_paths]; then the final log-price x_N and the fixing sum A = sum e^{x}
+// (zero for a European), each [n_paths].
+__host__ __device__ inline uint64_t ckpt_count(uint32_t n_steps, uint32_t every)
+{
+    return (n_steps + every - 1) / every;
+}
+inline uint64_t ckpt_bytes(uint64_t n_paths, uint32_t n_steps, uint32_t every, size_t real)
+{
+    return (2 * ckpt_count(n_steps, every) + 2) * n_paths * real;
+}
+
+// Adjoint sums: price and the derivatives of the discounted payoff with respect
+// to (S0, v0, r, kappa, theta, sigma, rho), each as (sum, sum of squares).
+enum AdjointOut : int { ADJ_PRICE = 0, ADJ_S0, ADJ_V0, ADJ_R, ADJ_KAPPA, ADJ_THETA, ADJ_SIGMA, ADJ_RHO };
+
+// Launches the reverse sweep over the checkpoints written by the forward
+// launch `L` (same request, L.ckpt set); block partials go to L.partials in the
+// N_ACC layout of AdjointOut; per_path (nullable) receives [n_paths][8]
+// (payoff and the seven derivatives) scaled by `seed_grad`.
+hipError_t launch_adjoint(const PriceLaunch &L, double seed_grad, double *per_path,
+                          hipStream_t stream);
+
+// Plain bump-and-revalue: per-path central differences of n_bump pairs of
+// payoff rows.  pay = [1 + 2 n_bump][n_paths] (row 0 the base scenario, rows
+// 1+2b and 2+2b the up and down revaluations of bump b).  Each block writes a
+// BUMP_W-double partial record: [0], [1] sum and sum of squares of the base
+// payoff; then for bump b at 2 + 4b: sum and sum of squares of
+// (up - down) * scale1[b], then of (up - 2 base + down) * scale2[b].
+constexpr int MAX_BUMPS = 8;
+constexpr int BUMP_W = 2 + 4 * MAX_BUMPS;
+struct BumpScales {
+    double first[MAX_BUMPS], second[MAX_BUMPS];
+};
+hipError_t launch_bump_combine(const double *pay, uint64_t n_paths, uint32_t n_bump,
+                               const BumpScales &sc, double *partials, uint32_t blocks,
+                               hipStream_t stream);
+// Fixed-order sum of `rows` partial records of width w into out[w].
+hipError_t launch_reduce_rows(const double *partials, uint32_t rows, uint32_t w, double *out,
+                              hipStream_t stream);
 
 // Launches the path kernel of `L` on `stream` (one partial record per block).
 hipError_t launch_paths(const PriceLaunch &L, hipStream_t stream);

@@ -20,32 +20,10 @@
 // partial record; a second kernel sums the partials in a fixed order.
 #include "device_math.hpp"
 #include "internal.hpp"
+#include "path_step.hpp"
 
 namespace heston {
 namespace {
-
-template <class R> struct Coef {
-    R dt, sqrt_dt, r_dt, half_dt, kdt, ktdt, qdt;
-};
-
-template <class R> __device__ __forceinline__ Coef<R> coef(const StepCoef &s)
-{
-    return Coef<R>{(R)s.dt, (R)s.sqrt_dt, (R)s.r_dt, (R)s.half_dt, (R)s.kappa_dt,
-                   (R)s.kappa_theta_dt, (R)s.quarter_sigma2_dt};
-}
-
-// One Milstein step of (x, V) on grid c.  sz2 = sigma Z2, mil = dt sigma^2/4 (Z2^2 - 1).
-template <class R, bool FT>
-__device__ __forceinline__ void mil_step(R &x, R &v, const Coef<R> &c, R z1, R sz2, R mil)
-{
-    const R vp = v > R(0) ? v : R(0);
-    const R s = fast_sqrt(vp * c.dt);
-    x += (c.r_dt - c.half_dt * vp) + s * z1;
-    const R vb = FT ? v : vp;
-    v = vb + (c.ktdt - c.kdt * vp) + sz2 * s + mil;
-    if (!FT)
-        v = v > R(0) ? v : R(0);
-}
 
 struct Payoff {
     int type;
@@ -125,7 +103,7 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         }
         if constexpr (ASIAN) {
             const uint32_t jf = j + 1;
-            const bool fix = L.fix_bits == nullptr || ((L.fix_bits[jf >> 5] >> (jf & 31u)) & 1u);
+            const bool fix = is_fixing(L.fix_bits, jf);
             if (fix) {
                 const R e = fast_exp(x);
                 const R t = (R)jf * cb.dt;
@@ -150,8 +128,15 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         // Philox: counter (j >> 1, lo32 p, hi32 p, 0); words (0,1) even step, (2,3) odd step.
         const uint32_t k0 = (uint32_t)L.seed, k1 = (uint32_t)(L.seed >> 32);
         const uint32_t plo = (uint32_t)p, phi = (uint32_t)(p >> 32);
+        R *ck = reinterpret_cast<R *>(L.ckpt);
+        const uint64_t np = L.n_paths, row = p - L.first_path;
         uint32_t j = 0;
         for (; j + 1 < N; j += 2) {
+            if (ck != nullptr && j % L.ckpt_every == 0 && active) {
+                const uint64_t c = j / L.ckpt_every;
+                ck[(2 * c) * np + row] = x;
+                ck[(2 * c + 1) * np + row] = v;
+            }
             const U4 w = philox4x32_10(U4{j >> 1, plo, phi, 0u}, k0, k1);
             R za, zb;
             if constexpr (sizeof(R) == 4)
@@ -166,6 +151,11 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
             step(j + 1, za, zb);
         }
         if (j < N) {
+            if (ck != nullptr && j % L.ckpt_every == 0 && active) {
+                const uint64_t c = j / L.ckpt_every;
+                ck[(2 * c) * np + row] = x;
+                ck[(2 * c + 1) * np + row] = v;
+            }
             const U4 w = philox4x32_10(U4{j >> 1, plo, phi, 0u}, k0, k1);
             R za, zb;
             if constexpr (sizeof(R) == 4)
@@ -173,6 +163,11 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
             else
                 box_muller(uniform_f64(w.x), uniform_f64(w.y), za, zb);
             step(j, za, zb);
+        }
+        if (ck != nullptr && active) {
+            const uint64_t c = ckpt_count(N, L.ckpt_every);
+            ck[(2 * c) * np + row] = x;
+            ck[(2 * c + 1) * np + row] = A;
         }
     } else {
         // Sobol point i of replicate `rep`, Brownian bridge walked in time order
@@ -284,6 +279,9 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
             y[e] = 0.0;
     }
 
+    if (L.pay_out != nullptr && active)
+        L.pay_out[p - L.first_path] = y[EST_PRICE];
+
     if (L.dump != nullptr && active) {
         double *rec = L.dump + (p - L.first_path) * DUMP_WIDTH;
         rec[0] = ST;
@@ -352,6 +350,66 @@ __global__ __launch_bounds__(BLOCK) void reduce_partials(const double *__restric
         rep_sums[(uint64_t)blockIdx.x * N_ACC + threadIdx.x] = red[0][threadIdx.x];
 }
 
+// Plain bump-and-revalue: per-path central differences of stored payoff rows.
+__global__ __launch_bounds__(BLOCK) void bump_combine_kernel(const double *__restrict__ pay,
+                                                             uint64_t n, uint32_t n_bump,
+                                                             const BumpScales sc,
+                                                             double *__restrict__ partials)
+{
+    __shared__ double red[BLOCK / 64][BUMP_W];
+    double acc[BUMP_W];
+#pragma unroll
+    for (int k = 0; k < BUMP_W; ++k)
+        acc[k] = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) {
+        const double b = pay[i];
+        acc[0] += b;
+        acc[1] += b * b;
+#pragma unroll
+        for (int k = 0; k < MAX_BUMPS; ++k) {
+            if (k < (int)n_bump) {
+                const double u = pay[(1 + 2 * (uint64_t)k) * n + i];
+                const double d = pay[(2 + 2 * (uint64_t)k) * n + i];
+                const double g1 = (u - d) * sc.first[k];
+                const double g2 = (u - 2.0 * b + d) * sc.second[k];
+                acc[2 + 4 * k] += g1;
+                acc[3 + 4 * k] += g1 * g1;
+                acc[4 + 4 * k] += g2;
+                acc[5 + 4 * k] += g2 * g2;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < BUMP_W; ++k) {
+        const double t = wave_sum(acc[k]);
+        if (lane == 0)
+            red[wave][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < BUMP_W) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w)
+            t += red[w][threadIdx.x];
+        partials[(uint64_t)blockIdx.x * BUMP_W + threadIdx.x] = t;
+    }
+}
+
+// Fixed-order sum of `rows` records of width w (w <= BLOCK): thread k sums column k.
+__global__ __launch_bounds__(BLOCK) void reduce_rows_kernel(const double *__restrict__ partials,
+                                                            uint32_t rows, uint32_t w,
+                                                            double *__restrict__ out)
+{
+    if (threadIdx.x >= w)
+        return;
+    double t = 0.0;
+    for (uint32_t r = 0; r < rows; ++r)
+        t += partials[(uint64_t)r * w + threadIdx.x];
+    out[threadIdx.x] = t;
+}
+
 // Digital shifts of the Sobol replicates: shift[r][d] = top 30 bits of word 0
 // of Philox4x32-10(counter (d, r, 0, 1), key = seed).
 __global__ void sobol_shift_kernel(uint64_t seed, uint32_t dims, uint32_t reps, uint32_t *out)
@@ -411,6 +469,23 @@ hipError_t launch_sobol_shifts(uint64_t seed, uint32_t dims, uint32_t reps, uint
 hipError_t launch_paths(const PriceLaunch &L, hipStream_t stream)
 {
     return L.precision == 0 ? launch_r<double>(L, stream) : launch_r<float>(L, stream);
+}
+
+hipError_t launch_bump_combine(const double *pay, uint64_t n_paths, uint32_t n_bump,
+                               const BumpScales &sc, double *partials, uint32_t blocks,
+                               hipStream_t stream)
+{
+    hipLaunchKernelGGL(bump_combine_kernel, dim3(blocks), dim3(BLOCK), 0, stream, pay, n_paths,
+                       n_bump, sc, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_rows(const double *partials, uint32_t rows, uint32_t w, double *out,
+                              hipStream_t stream)
+{
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(BLOCK), 0, stream, partials, rows, w,
+                       out);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce(const PriceLaunch &L, double *rep_sums, hipStream_t stream)

@@ -1,0 +1,220 @@
+"""GPU parity of the adjoint (reverse-mode) kernel and of plain bump-and-revalue.
+
+Per-path derivatives from heston_adjoint_backward against the oracle's
+forward-mode derivatives (which are pinned to finite differences in
+test_oracle.py), with |gpu - oracle| <= tol max(|oracle|, floor) max(1, a_p):
+floors 1 for d/dS0, S0 for d/dv0, d/dsigma and d/drho, K T for d/dr, S0 T for
+d/dkappa and d/dtheta; tol 1e-12 in FP64, 1e-5 in FP32.  a_p is the path's
+largest factor d sqrt(V+ dt)/dV+ = sqrt(dt/V+)/2 (reported by the oracle):
+both sweeps multiply by it where the variance nears zero, so it scales how
+far their different rounding orders can drift apart (observed: FP64
+differences up to 2.8e-11 relative on paths with a_p = 308; a_p has median
+~5 and 99th percentile ~50 at these parameters).  Payoffs keep the plain bar.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import BASE, PAPER
+
+pytestmark = pytest.mark.gpu
+
+PB = oracle.Params(**BASE)
+PP = oracle.Params(**PAPER)
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_10477_amd as hm
+    hm.lib()
+    return hm
+
+
+@pytest.fixture(scope="module")
+def ctx(hm):
+    c = hm.Context(0)
+    yield c
+    c.close()
+
+
+def adjoint_per_path(hm, ctx, p, opt_type, n, N, seed, prec, every, scheme=0, fixings=None,
+                     dprice=1.0):
+    import torch
+    opts = hm.Options(precision=prec, scheme=scheme, greeks=hm.GREEKS_PATHWISE, fixings=fixings)
+    ck = torch.empty(hm.ckpt_bytes(n, N, every, prec), dtype=torch.uint8, device="cuda:0")
+    price, _ = ctx.adjoint_forward(p.__dict__, opt_type, n, N, seed, ck, every, opts)
+    pp = torch.empty((n, 8), dtype=torch.float64, device="cuda:0")
+    grads, _ = ctx.adjoint_backward(p.__dict__, opt_type, n, N, seed, ck, every, dprice, opts,
+                                    per_path=pp)
+    return price, grads, pp.cpu().numpy()
+
+
+def check_against_tangent(d, p, opt_type, N, seed, first, n, prec, scheme, fixings, scale=1.0):
+    tol = TOL[prec]
+    mode = oracle.ABSORB if scheme == 1 else oracle.FULL_TRUNC
+    tan = oracle.tangent(p, opt_type, N, seed, first, n, mode, fixings, threads=8)
+    rec = oracle.simulate(p, opt_type, N, seed, first, n, mode, fixings, threads=8)
+    near = np.abs(rec[:, 2] - p.K) < 1e3 * tol * p.K
+    amp = np.maximum(1.0, tan[:, 8])
+    floors = [p.S0, 1.0, p.S0, p.K * p.T, p.S0 * p.T, p.S0 * p.T, p.S0, p.S0]
+    names = ["pay", "S0", "v0", "r", "kappa", "theta", "sigma", "rho"]
+    for k in range(8):
+        o = tan[:, k] * (scale if k else 1.0)
+        g = d[:, k]
+        err = np.abs(g - o) / np.maximum(np.abs(o), floors[k]) / (amp if k else 1.0)
+        bad = (err > tol) & ~near
+        assert not bad.any(), (names[k], int(bad.sum()), float(err[bad].max()),
+                               int(np.argmax(np.where(bad, err, 0))))
+
+
+@pytest.mark.parametrize("opt_type", [0, 1, 2, 3])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_adjoint_fp64_matches_tangent(hm, ctx, opt_type, scheme):
+    n, N, seed = 2000 + 13, 37, 11
+    p = PP if scheme == 1 else PB.replace(sigma=0.6)
+    fix = (3, 10, 20, 37) if opt_type >= 2 else None
+    price, grads, d = adjoint_per_path(hm, ctx, p, opt_type, n, N, seed, 0, 8, scheme, fix)
+    check_against_tangent(d, p, opt_type, N, seed, 0, n, 0, scheme, fix)
+    for k in range(7):
+        m, se = oracle.mean_se(d[:, 1 + k])
+        assert grads[k][0] == pytest.approx(m, rel=1e-10, abs=1e-12)
+        assert grads[k][1] == pytest.approx(se, rel=1e-6, abs=1e-12)
+
+
+@pytest.mark.parametrize("every", [8, 16])
+@pytest.mark.parametrize("opt_type", [0, 2])
+def test_adjoint_fp32_matches_tangent(hm, ctx, every, opt_type):
+    n, N, seed = 4096 + 100, 100, 5
+    price, grads, d = adjoint_per_path(hm, ctx, PB, opt_type, n, N, seed, 1, every)
+    check_against_tangent(d, PB, opt_type, N, seed, 0, n, 1, 0, None)
+
+
+def test_adjoint_seed_gradient_scales(hm, ctx):
+    n, N = 1000, 20
+    _, g1, d1 = adjoint_per_path(hm, ctx, PB, 0, n, N, 3, 0, 8)
+    _, g2, d2 = adjoint_per_path(hm, ctx, PB, 0, n, N, 3, 0, 8, dprice=-2.5)
+    assert np.allclose(d2[:, 1:], -2.5 * d1[:, 1:], rtol=1e-15, atol=0)
+    assert np.allclose(d2[:, 0], d1[:, 0])
+
+
+def test_adjoint_S0_and_r_equal_pathwise_estimators(hm, ctx):
+    """d/dS0 and d/dr of the adjoint are the paper's pathwise Delta and Rho."""
+    n, N, seed = 5000, 64, 21
+    for opt_type in (0, 1, 2, 3):
+        _, _, d = adjoint_per_path(hm, ctx, PB, opt_type, n, N, seed, 0, 16)
+        dump = ctx.dump_paths(PB.__dict__, opt_type, n, N, seed, 0, n,
+                              hm.Options(greeks=hm.GREEKS_PATHWISE)).cpu().numpy()
+        assert np.allclose(d[:, 1], dump[:, 4], rtol=1e-12, atol=1e-14)
+        assert np.allclose(d[:, 3], dump[:, 5], rtol=1e-11, atol=1e-11)
+
+
+def test_adjoint_large_sampled(hm, ctx):
+    """The 2^22-path x 365-step FP32 adjoint (checkpoints every 16 steps), in the
+    configuration the benchmark times: sampled windows against the oracle's
+    derivatives, and the reduced gradients against the per-path values."""
+    import torch
+    n, N, seed = 1 << 22, 365, 42
+    for opt_type in (0, 2):
+        price, grads, d = adjoint_per_path(hm, ctx, PB, opt_type, n, N, seed, 1, 16)
+        for first in (0, n // 3, n - 600):
+            check_against_tangent(d[first:first + 600], PB, opt_type, N, seed, first, 600, 1, 0,
+                                  None)
+        for k in range(7):
+            m, se = oracle.mean_se(d[:, 1 + k])
+            assert grads[k][0] == pytest.approx(m, rel=1e-9, abs=1e-12)
+        del d
+        torch.cuda.empty_cache()
+
+
+def test_adjoint_against_analytic(hm, ctx):
+    """FP32, 2^20 paths x 200 steps: the seven European-call sensitivities within
+    4 SE plus a discretisation allowance of the characteristic-function values."""
+    from oracle import analytic
+    g = analytic.heston_call_greeks(PB)
+    _, grads, _ = adjoint_per_path(hm, ctx, PB, 0, 1 << 20, 200, 42, 1, 16)
+    ref = [g["delta"], g["vega"], g["rho"], g["d_kappa"], g["d_theta"], g["d_sigma"], g["d_rho"]]
+    bias = [5e-4, 0.2, 0.1, 0.01, 0.2, 0.05, 0.05]
+    for k in range(7):
+        assert abs(grads[k][0] - ref[k]) < 4 * grads[k][1] + bias[k], (k, grads[k], ref[k])
+
+
+def test_autograd_function(hm, ctx):
+    import torch
+    from paper_2309_10477_amd.autograd import AdjointSpec, HestonAdjoint
+    theta = torch.tensor([PB.S0, PB.v0, PB.r, PB.kappa, PB.theta, PB.sigma, PB.rho],
+                         dtype=torch.float64, requires_grad=True)
+    spec = AdjointSpec(K=PB.K, T=PB.T, opt_type=2, n_paths=20000, n_steps=50, seed=4,
+                       precision=hm.FP64, every=8, ctx=ctx)
+    price = HestonAdjoint.apply(theta, spec)
+    (3.0 * price).backward()
+    n, N = 20000, 50
+    _, grads, d = adjoint_per_path(hm, ctx, PB, 2, n, N, 4, 0, 8)
+    assert float(price) == pytest.approx(d[:, 0].mean(), rel=1e-12)
+    assert np.allclose(theta.grad.numpy(), 3.0 * np.array([v for v, _ in grads]), rtol=1e-12)
+
+
+def test_invalid_adjoint_requests(hm, ctx):
+    import torch
+    ck = torch.empty(16, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(hm.HestonError):
+        ctx.adjoint_forward(BASE, 0, 1000, 10, 1, ck, 16)          # buffer too small
+    ck = torch.empty(hm.ckpt_bytes(1000, 10, 16, hm.FP32), dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(hm.HestonError):
+        ctx.adjoint_forward(BASE, 0, 1000, 10, 1, ck, 12)          # interval
+    with pytest.raises(hm.HestonError):
+        ctx.adjoint_forward(dict(BASE, rho=1.0), 0, 1000, 10, 1, ck, 16)
+
+
+# ---------------------------------------------------------------------------
+# Plain bump-and-revalue (nine independent revaluations)
+
+def test_plain_bumps_match_oracle_fp64(hm, ctx):
+    n, N, seed = 10_000, 100, 42
+    r = ctx.price_greeks(PB.__dict__, hm.EURO_CALL, n, N, seed,
+                         hm.Options(greeks=hm.GREEKS_PATHWISE | hm.GREEKS_BUMP_PLAIN))
+    ref = oracle.price_greeks(PB, oracle.EURO_CALL, n, N, seed, threads=8)
+    for k, (v, se) in ref.items():
+        assert r[k][0] == pytest.approx(v, rel=1e-10, abs=1e-11), k
+        assert r[k][1] == pytest.approx(se, rel=1e-6, abs=1e-12), k
+
+
+def test_plain_and_fused_bumps_agree_fp32_asian(hm, ctx):
+    n, N, seed = 1 << 16, 252, 42
+    a = ctx.price_greeks(PB.__dict__, hm.ASIAN_CALL, n, N, seed,
+                         hm.Options(precision=hm.FP32))
+    b = ctx.price_greeks(PB.__dict__, hm.ASIAN_CALL, n, N, seed,
+                         hm.Options(precision=hm.FP32, greeks=hm.GREEKS_PATHWISE |
+                                    hm.GREEKS_BUMP_PLAIN))
+    for k in ("price", "pw_delta", "pw_rho"):
+        assert a[k] == b[k], k
+    # the fused kernel evaluates the S0 and r scenarios algebraically from the
+    # FP32 state; the plain launches re-simulate them in FP32
+    for k in ("delta", "gamma", "vega", "rho", "theta"):
+        assert abs(a[k][0] - b[k][0]) < 0.05 * a[k][1] + 1e-6 * abs(a[k][0]), (k, a[k], b[k])
+
+
+def test_bump_revalue_seven_parameters(hm, ctx):
+    """General plain bumps of the seven adjoint inputs against the oracle's
+    central differences on the same paths (FP64)."""
+    n, N, seed = 3000, 30, 8
+    names = ["S0", "v0", "r", "kappa", "theta", "sigma", "rho"]
+    idx = [hm.P_S0, hm.P_V0, hm.P_R, hm.P_KAPPA, hm.P_THETA, hm.P_SIGMA, hm.P_RHO]
+    bumps = [(i, 0, 1e-3) for i in idx]
+    r = ctx.bump_revalue(PB.__dict__, hm.ASIAN_PUT, n, N, seed, bumps)
+    base = oracle.simulate(PB, oracle.ASIAN_PUT, N, seed, 0, n)[:, 3]
+    assert r["price"][0] == pytest.approx(base.mean(), rel=1e-12)
+    for k, name in enumerate(names):
+        up = oracle.simulate(PB.replace(**{name: getattr(PB, name) + 1e-3}), oracle.ASIAN_PUT, N,
+                             seed, 0, n)[:, 3]
+        dn = oracle.simulate(PB.replace(**{name: getattr(PB, name) - 1e-3}), oracle.ASIAN_PUT, N,
+                             seed, 0, n)[:, 3]
+        m, se = oracle.mean_se((up - dn) / 2e-3)
+        assert r["first"][k][0] == pytest.approx(m, rel=1e-8, abs=1e-9), name
+        m2, _ = oracle.mean_se((up - 2 * base + dn) / 1e-6)
+        assert r["second"][k][0] == pytest.approx(m2, rel=1e-5, abs=1e-4), name
