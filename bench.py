@@ -55,9 +55,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="qmc,adjoint",
-                    help="extra legs reported after the timed steps: qmc, adjoint, and copy "
-                         "(a 256 MiB device copy that calibrates HBM byte counters)")
+    ap.add_argument("--legs", default="qmc,adjoint,batch,serve",
+                    help="extra legs reported after the timed steps: qmc, adjoint, batch, serve, "
+                         "and copy (a 256 MiB device copy that calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -143,6 +143,76 @@ def adjoint_vs_bump(ctx, hm, torch):
     return out
 
 
+def portfolio_batch(ctx, hm, torch):
+    """The 4096-option portfolio (European/Asian calls and puts, K ~ U[70,130],
+    T ~ U[0.1,5], steps = ceil(252 T), paths 2^14..2^20, Heston parameters per
+    option) in one persistent launch, FP32 paths, FP64 sums, price + pathwise
+    Delta/Rho."""
+    from workloads import portfolio
+    pf = portfolio()
+    reqs = [dict(params=pf.params(i), type=int(pf.opt_type[i]), n_steps=int(pf.n_steps[i]),
+                 n_paths=int(pf.n_paths[i]), seed=int(pf.seed[i]), want=hm.WANT_PATHWISE)
+            for i in range(len(pf))]
+    opts = hm.Options(precision=hm.FP32, greeks=hm.GREEKS_PATHWISE)
+    ctx.price_batch(reqs[:64], opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, ms = ctx.price_batch(reqs, opts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ps = pf.path_steps()
+    return {"options": len(pf), "path_steps": ps, "wall_ms": wall * 1e3, "kernel_ms": ms,
+            "path_steps_per_s": ps / wall, "kernel_path_steps_per_s": ps / (ms * 1e-3)}
+
+
+def serving(ctx, hm, torch, n_measured=1000, n_warm=100):
+    """Continuous batching: requests (50/50 European/Asian, calls/puts, path cap
+    2^U[12,22], steps U{50..1000}, Heston parameters as the portfolio's, price
+    + seven adjoint sensitivities to a price SE of 0.1) arrive as a Poisson
+    stream at 0.5 and 0.8 of the saturated request rate, which is measured
+    first from a burst.  Latency = heston_submit to completion."""
+    from workloads import request_stream
+
+    def to_reqs(rs):
+        return [dict(params=rs.params[i], type=int(rs.opt_type[i]), n_steps=int(rs.n_steps[i]),
+                     n_paths=int(rs.path_cap[i]), seed=int(rs.seed[i]), want=hm.WANT_ADJOINT,
+                     se_target=rs.se_target) for i in range(len(rs.params))]
+
+    def run(reqs, arrivals):
+        srv = hm.Server(ctx, precision=hm.FP32, max_steps=1000)
+        try:
+            t0 = time.perf_counter()
+            tickets = []
+            for q, a in zip(reqs, arrivals):
+                while time.perf_counter() - t0 < a:
+                    pass
+                tickets.append(srv.submit(**q))
+            res = [srv.wait(t, 300_000) for t in tickets]
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        finally:
+            srv.close()
+        return res, wall, st
+
+    burst = request_stream(400, 1.0, seed=5)
+    res, wall, st = run(to_reqs(burst), np.zeros(400))
+    mu = 400 / wall
+    out = {"saturated_requests_per_s": mu,
+           "saturated_path_steps_per_s": st["path_steps"] / wall,
+           "mean_paths_used": float(np.mean([r["n_paths"] for r in res]))}
+    for frac in (0.5, 0.8):
+        rs = request_stream(n_warm + n_measured, frac * mu, seed=6)
+        res, wall, st = run(to_reqs(rs), rs.arrival_s)
+        lat = np.array([r["device_ms"] for r in res[n_warm:]])
+        out[f"load_{frac}"] = {
+            "arrival_rate_per_s": frac * mu, "requests": n_measured,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "throughput_requests_per_s": len(res) / wall,
+            "path_steps_per_s": st["path_steps"] / wall, "launches": st["launches"],
+            "gpu_busy_frac": st["busy_ms"] * 1e-3 / wall}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -217,6 +287,10 @@ def main():
                                    "price": rq["price"], "replicates": QMC_REPLICATES}
     if "adjoint" in legs:
         out["adjoint_vs_bump"] = adjoint_vs_bump(ctx, hm, torch)
+    if "batch" in legs:
+        out["portfolio_batch"] = portfolio_batch(ctx, hm, torch)
+    if "serve" in legs:
+        out["serving"] = serving(ctx, hm, torch)
     if "copy" in legs:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
         dst = torch.empty_like(src)

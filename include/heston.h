@@ -89,7 +89,8 @@ enum {
 enum {
     HESTON_VALID_PRICE = 1u,
     HESTON_VALID_PATHWISE = 2u,
-    HESTON_VALID_BUMPS = 4u
+    HESTON_VALID_BUMPS = 4u,
+    HESTON_VALID_ADJOINT = 8u
 };
 
 typedef struct heston_est {
@@ -102,7 +103,8 @@ typedef struct heston_result {
     heston_est price;
     heston_est delta, gamma, vega, rho, theta; /* bump-and-revalue; vega = dP/dv0, theta = -dP/dT */
     heston_est pw_delta, pw_rho;               /* paper's pathwise estimators                  */
-    uint64_t n_paths;
+    heston_est adj[7]; /* adjoint dP/d(S0, v0, r, kappa, theta, sigma, rho) (batches, serving) */
+    uint64_t n_paths;  /* paths the estimates use                                            */
     uint32_t valid_mask;
     uint32_t reserved;
     double device_ms; /* GPU time of the path kernel, HIP events on the context stream */
@@ -243,6 +245,99 @@ heston_status heston_adjoint_backward(heston_ctx *ctx, const heston_params *para
                                       uint32_t every, const void *ckpt_dev, uint64_t ckpt_bytes,
                                       double dprice, heston_est grads[7], double *per_path_dev,
                                       double *device_ms);
+
+/* ------------------------------------------------------------------------
+ * Batched pricing: many options of different sizes in one persistent launch.
+ *
+ * A request names one option, its path count and step count, its own seed
+ * (its paths are paths 0 .. n_paths-1 of that seed's stream, as for
+ * heston_price_greeks_ex) and what it wants: the price with the pathwise
+ * Delta/Rho, or the price with the seven adjoint sensitivities (then the
+ * pathwise Delta/Rho equal the adjoint dS0/dr).  Asian requests fix at every
+ * step.  Work is split into items of 1024 paths; each request's result sums
+ * its items in item order, so it is bitwise the same whether it is priced
+ * alone or in any batch. */
+enum { HESTON_WANT_PATHWISE = 1u, HESTON_WANT_ADJOINT = 2u };
+
+typedef struct heston_request {
+    heston_params params;
+    int32_t type;       /* heston_option_type                                   */
+    uint32_t n_steps;
+    uint64_t n_paths;   /* paths (serving: the cap)                             */
+    uint64_t seed;
+    uint32_t want;      /* HESTON_WANT_PATHWISE or HESTON_WANT_ADJOINT          */
+    uint32_t reserved;
+    double se_target;   /* serving: stop at the first item boundary where the
+                           price SE <= se_target (0: run all n_paths)          */
+} heston_request;
+
+/* Prices reqs[0..n-1] (host array) into out[0..n-1] (host array).  opts
+ * (nullable) supplies precision and truncation; Philox normals only; opts
+ * fixing_steps must be NULL.  Blocks until done; device_ms (nullable) gets the
+ * GPU time of the batched kernels.  Errors: INVALID_ARGUMENT (any request
+ * invalid; nothing is priced), UNSUPPORTED, OVER_BUDGET / OUT_OF_MEMORY
+ * (item records: 128 bytes per 1024 paths), DEVICE_ERROR. */
+heston_status heston_price_batch(heston_ctx *ctx, const heston_request *reqs, uint32_t n,
+                                 const heston_opts *opts, heston_result *out, double *device_ms);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of pricing requests.
+ *
+ * A server owns an engine thread and device memory on the context's device.
+ * heston_submit enqueues a request and returns at once with a ticket.  The
+ * engine admits queued requests while the server's device-memory budget and
+ * request slots allow (a request holds 128 bytes per 1024-path item of its path
+ * cap plus a 256-byte state), and repeatedly launches the batched kernel over
+ * the next items of every admitted request, so requests that arrive while
+ * others run join the next launch and their work overlaps on the device.
+ * Each request's running sums live on the device and are extended item by
+ * item, in item order, by a fold kernel that also applies the stopping rule:
+ * the request completes at the first item boundary (at least two items) where
+ * the price SE is <= se_target, or at its path cap.  Its result therefore
+ * depends only on its own items and is bitwise the same however it was
+ * batched.  Latency = completion seen by the engine - heston_submit call. */
+typedef struct heston_server heston_server;
+
+typedef struct heston_server_config {
+    uint32_t struct_size;       /* sizeof(heston_server_config)                    */
+    int32_t precision;          /* HESTON_FP32 (default) or HESTON_FP64            */
+    int32_t scheme;             /* HESTON_FULL_TRUNCATION (default) / ABSORPTION   */
+    uint32_t max_active;        /* admitted requests at once (default 4096)        */
+    uint32_t max_steps;         /* largest n_steps accepted (default 2048)         */
+    uint32_t reserved;
+    uint64_t hbm_budget_bytes;  /* device memory for request state and launch
+                                   buffers (default 8 GiB)                        */
+    uint64_t launch_path_steps; /* work per launch (default 2^31 path-steps)      */
+} heston_server_config;
+
+typedef struct heston_server_stats {
+    uint64_t submitted, admitted, completed, queued, active;
+    uint64_t launches;
+    double path_steps;          /* path-steps simulated (items launched)           */
+    double busy_ms;             /* GPU time of the batched and fold kernels        */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* latency of completed requests       */
+    uint64_t pool_bytes;        /* device memory for request states (the budget
+                                   minus adjoint scratch and launch buffers)     */
+    uint64_t pool_free_bytes;
+} heston_server_stats;
+
+heston_status heston_server_default_config(heston_server_config *cfg);
+/* Errors: INVALID_ARGUMENT, OVER_BUDGET (the budget cannot hold the launch
+ * buffers), OUT_OF_MEMORY, DEVICE_ERROR. */
+heston_status heston_server_create(heston_ctx *ctx, const heston_server_config *cfg,
+                                   heston_server **out);
+/* Stops the engine after the work in flight; pending requests are dropped. */
+heston_status heston_server_destroy(heston_server *srv);
+/* INVALID_ARGUMENT for a bad request (its want, params, n_steps > max_steps, or
+ * a path cap whose state alone exceeds the budget). */
+heston_status heston_submit(heston_server *srv, const heston_request *req, uint64_t *ticket);
+/* HESTON_OK and *out when done (the ticket is then released), HESTON_PENDING
+ * while queued or running, HESTON_NOT_FOUND for an unknown ticket. */
+heston_status heston_poll(heston_server *srv, uint64_t ticket, heston_result *out);
+/* Blocks until the ticket is done (or timeout_ms elapses: HESTON_PENDING). */
+heston_status heston_wait(heston_server *srv, uint64_t ticket, double timeout_ms,
+                          heston_result *out);
+heston_status heston_server_get_stats(heston_server *srv, heston_server_stats *out);
 
 /* Static description of a status code; never NULL. */
 const char *heston_status_str(heston_status status);

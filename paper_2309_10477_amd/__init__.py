@@ -48,7 +48,7 @@ class CEst(ctypes.Structure):
 
 
 class CResult(ctypes.Structure):
-    _fields_ = [(n, CEst) for n in EST_NAMES] + [
+    _fields_ = [(n, CEst) for n in EST_NAMES] + [("adj", CEst * 7),
         ("n_paths", ctypes.c_uint64), ("valid_mask", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32), ("device_ms", ctypes.c_double)]
 
@@ -62,6 +62,31 @@ class COpts(ctypes.Structure):
         ("fixing_steps", ctypes.POINTER(ctypes.c_uint32)), ("n_fixings", ctypes.c_uint32),
         ("bump_S0_rel", ctypes.c_double), ("bump_v0_rel", ctypes.c_double),
         ("bump_r_abs", ctypes.c_double), ("bump_T_abs", ctypes.c_double)]
+
+
+class CRequest(ctypes.Structure):
+    _fields_ = [("params", CParams), ("type", ctypes.c_int32), ("n_steps", ctypes.c_uint32),
+                ("n_paths", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("want", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("se_target", ctypes.c_double)]
+
+
+WANT_PATHWISE, WANT_ADJOINT = 1, 2
+
+
+class CServerConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("scheme", ctypes.c_int32), ("max_active", ctypes.c_uint32),
+                ("max_steps", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("launch_path_steps", ctypes.c_uint64)]
+
+
+class CServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "admitted", "completed", "queued",
+                                               "active", "launches")] + \
+        [(n, ctypes.c_double) for n in ("path_steps", "busy_ms", "p50_ms", "p99_ms", "mean_ms",
+                                        "max_ms")] + \
+        [(n, ctypes.c_uint64) for n in ("pool_bytes", "pool_free_bytes")]
 
 
 class CBump(ctypes.Structure):
@@ -110,6 +135,15 @@ def lib():
                                           c.c_uint32, c.c_uint64, P(COpts), c.c_uint32,
                                           c.c_void_p, c.c_uint64, c.c_double, P(CEst),
                                           c.c_void_p, P(c.c_double)]
+    L.heston_price_batch.argtypes = [c.c_void_p, P(CRequest), c.c_uint32, P(COpts), P(CResult),
+                                     P(c.c_double)]
+    L.heston_server_default_config.argtypes = [P(CServerConfig)]
+    L.heston_server_create.argtypes = [c.c_void_p, P(CServerConfig), P(c.c_void_p)]
+    L.heston_server_destroy.argtypes = [c.c_void_p]
+    L.heston_submit.argtypes = [c.c_void_p, P(CRequest), P(c.c_uint64)]
+    L.heston_poll.argtypes = [c.c_void_p, c.c_uint64, P(CResult)]
+    L.heston_wait.argtypes = [c.c_void_p, c.c_uint64, c.c_double, P(CResult)]
+    L.heston_server_get_stats.argtypes = [c.c_void_p, P(CServerStats)]
     _lib = L
     return L
 
@@ -281,6 +315,25 @@ class Context:
         return [(g.value, g.std_err) for g in grads], ms.value
 
 
+    def price_batch(self, requests, opts: Options | None = None):
+        """requests: list of dicts with params (dict), type, n_steps, n_paths, seed,
+        want (WANT_PATHWISE | WANT_ADJOINT).  Returns ([result dicts], device_ms)."""
+        arr = (CRequest * len(requests))()
+        for i, q in enumerate(requests):
+            arr[i] = make_request(**q)
+        out = (CResult * len(requests))()
+        ms = ctypes.c_double()
+        o = _OptsHolder(opts or Options(precision=FP32, greeks=GREEKS_PATHWISE), 1)
+        check(lib().heston_price_batch(self.handle, arr, len(requests), ctypes.byref(o.c), out,
+                                       ctypes.byref(ms)))
+        return [_result_dict(r) for r in out], ms.value
+
+
+def make_request(params, type, n_steps, n_paths, seed, want=1, se_target=0.0) -> CRequest:
+    return CRequest(_cparams(params), int(type), int(n_steps), int(n_paths), int(seed),
+                    int(want), 0, float(se_target))
+
+
 def ckpt_bytes(n_paths: int, n_steps: int, every: int = 16, precision: int = FP32) -> int:
     return int(lib().heston_adjoint_ckpt_bytes(n_paths, n_steps, every, precision))
 
@@ -290,6 +343,7 @@ def _result_dict(res: CResult) -> dict:
     for n in EST_NAMES:
         e = getattr(res, n)
         out[n] = (e.value, e.std_err)
+    out["adj"] = [(res.adj[k].value, res.adj[k].std_err) for k in range(7)]
     out["valid_mask"] = res.valid_mask
     out["n_paths"] = res.n_paths
     out["device_ms"] = res.device_ms
@@ -303,3 +357,59 @@ def price_greeks(params, opt_type: int, n_paths: int, n_steps: int, seed: int) -
     check(lib().heston_price_greeks(ctypes.byref(cp), opt_type, n_paths, n_steps, seed,
                                     ctypes.byref(res)))
     return _result_dict(res)
+
+
+class Server:
+    """Continuous-batching request loop of the library (heston_server_*): the
+    engine runs natively; submit() returns a ticket at once."""
+
+    def __init__(self, ctx: Context, precision: int = FP32, scheme: int = FULL_TRUNCATION,
+                 max_active: int = 4096, max_steps: int = 2048, hbm_budget_bytes: int = 8 << 30,
+                 launch_path_steps: int = 1 << 31):
+        cfg = CServerConfig()
+        check(lib().heston_server_default_config(ctypes.byref(cfg)))
+        cfg.precision, cfg.scheme, cfg.max_active, cfg.max_steps = (precision, scheme,
+                                                                    max_active, max_steps)
+        cfg.hbm_budget_bytes, cfg.launch_path_steps = hbm_budget_bytes, launch_path_steps
+        h = ctypes.c_void_p()
+        check(lib().heston_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+
+    def submit(self, **request) -> int:
+        t = ctypes.c_uint64()
+        q = make_request(**request)
+        check(lib().heston_submit(self.handle, ctypes.byref(q), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        res = CResult()
+        st = lib().heston_poll(self.handle, ticket, ctypes.byref(res))
+        if st == 1:
+            return None
+        check(st)
+        return _result_dict(res)
+
+    def wait(self, ticket: int, timeout_ms: float = 60_000.0):
+        res = CResult()
+        st = lib().heston_wait(self.handle, ticket, timeout_ms, ctypes.byref(res))
+        if st == 1:
+            return None
+        check(st)
+        return _result_dict(res)
+
+    def stats(self) -> dict:
+        st = CServerStats()
+        check(lib().heston_server_get_stats(self.handle, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in CServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            check(lib().heston_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

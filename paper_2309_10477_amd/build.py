@@ -10,7 +10,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = [os.path.join(HERE, "csrc", f) for f in ("api.hip", "price_kernel.hip",
-                                               "adjoint_kernel.hip")]
+                                               "adjoint_kernel.hip", "batch_kernel.hip",
+                                               "batch_api.hip", "server.hip")]
 HDRS = [os.path.join(HERE, "csrc", f) for f in ("internal.hpp", "device_math.hpp",
                                                 "path_step.hpp")] + \
     [os.path.join(os.path.dirname(HERE), "include", "heston.h")]

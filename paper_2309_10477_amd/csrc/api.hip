@@ -12,10 +12,12 @@
 
 #include "../../include/heston.h"
 #include "internal.hpp"
+#include "runtime.hpp"
 
 using namespace heston;
 
-namespace {
+namespace heston {
+namespace rt {
 
 thread_local std::string g_last_error;
 
@@ -24,36 +26,6 @@ heston_status fail(heston_status st, const std::string &msg)
     g_last_error = msg;
     return st;
 }
-
-#define HIP_TRY(expr)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess)                                                                      \
-            return fail(e_ == hipErrorOutOfMemory ? HESTON_OUT_OF_MEMORY : HESTON_DEVICE_ERROR,   \
-                        std::string(#expr) + ": " + hipGetErrorString(e_));                        \
-    } while (0)
-
-// A device buffer that only grows; its bytes count against the context budget.
-struct DevBuf {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-};
-
-} // namespace
-
-struct heston_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    uint64_t budget = 0;  // 0 = unlimited
-    uint64_t in_use = 0;  // bytes held by the buffers below
-    DevBuf partials, rep_sums, fix_bits, sobol_dirs, sobol_shift, bridge_start, bridge_ops;
-    DevBuf pay, bump_partials, bump_sums;
-    double *host_sums = nullptr; // pinned
-    size_t host_sums_bytes = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-};
-
-namespace {
 
 heston_status reserve(heston_ctx *c, DevBuf &b, size_t bytes)
 {
@@ -76,21 +48,6 @@ heston_status reserve(heston_ctx *c, DevBuf &b, size_t bytes)
     return HESTON_OK;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) == hipSuccess && prev != dev)
-            (void)hipSetDevice(dev);
-        else
-            prev = -1;
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0)
-            (void)hipSetDevice(prev);
-    }
-};
 
 bool finite_all(const heston_params *p)
 {
@@ -195,14 +152,6 @@ bool bridge_program(uint32_t N, BridgePlan &plan)
     return plan.ops.size() == (size_t)(N - 1);
 }
 
-struct Request {
-    heston_params p;
-    int type;
-    uint64_t n_paths;
-    uint32_t n_steps;
-    uint64_t seed;
-    heston_opts o;
-};
 
 heston_status check_request(const Request &q)
 {
@@ -534,7 +483,10 @@ heston_status check_adjoint(const Request &q, uint32_t every, const void *ckpt, 
     return HESTON_OK;
 }
 
-} // namespace
+} // namespace rt
+} // namespace heston
+
+using namespace heston::rt;
 
 extern "C" {
 
@@ -587,7 +539,8 @@ heston_status heston_ctx_destroy(heston_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift,
                       &c->bridge_start, &c->bridge_ops, &c->pay, &c->bump_partials,
-                      &c->bump_sums})
+                      &c->bump_sums, &c->batch_opts, &c->batch_items, &c->batch_partials,
+                      &c->batch_sums, &c->batch_counter, &c->batch_scratch})
         if (b->ptr)
             (void)hipFree(b->ptr);
     if (c->host_sums)

@@ -1,0 +1,183 @@
+// Persistent batched kernel: many options of different sizes in one launch.
+//
+// The work is a list of items; item g is chunk chunk_base[o] + (g - first_item[o])
+// of option o = item_opt[g], i.e. paths [chunk * CHUNK, (chunk + 1) * CHUNK) of
+// that option's own stream.  A grid sized to the resident capacity of the chip
+// pops item indices from one device counter until the list is exhausted, so
+// every workgroup ends when the counter passes the last item.  Items are
+// ordered by decreasing cost (longest step counts first), so the tail of the
+// launch holds the cheapest items.  Each item writes one FP64 partial record;
+// a second kernel sums every option's records in item order.  The partial of
+// an item depends only on its own paths and the option's sum only on the
+// item order, so an option's result is bitwise the same alone or in any batch.
+//
+// Per item and path: the Milstein path of the paper's algorithm "Milstein
+// approximation under Heston model" in R, payoff and pathwise estimators in
+// FP64; in adjoint mode the path's forward pass also stores checkpoints in
+// the workgroup's scratch slot and the reverse sweep follows immediately.
+#include "device_math.hpp"
+#include "internal.hpp"
+#include "path_step.hpp"
+
+namespace heston {
+namespace {
+
+template <class R, bool ASIAN, bool FT, bool ADJ>
+__device__ __forceinline__ void run_item_paths(const BatchOption &op, uint64_t chunk, R *scratch,
+                                               double acc[N_ACC])
+{
+    const uint32_t tid = threadIdx.x;
+#pragma unroll 1
+    for (uint32_t sub = 0; sub < BATCH_CHUNK / BLOCK; ++sub) {
+        const uint64_t p = chunk * BATCH_CHUNK + (uint64_t)sub * BLOCK + tid;
+        const bool active = p < op.n_paths;
+        double out[8];
+        if constexpr (ADJ) {
+            R x, v, A, B;
+            forward_path<R, ASIAN, FT>(op.k, p, x, v, A, B, scratch, BLOCK, tid, BATCH_CKPT_EVERY);
+            __threadfence_block();
+            adjoint_path<R, ASIAN, FT, BATCH_CKPT_EVERY>(op.k, p, scratch, BLOCK, tid, out);
+        } else {
+            R x, v, A, B;
+            forward_path<R, ASIAN, FT>(op.k, p, x, v, A, B, nullptr, 0, 0, 2);
+            path_estimators<ASIAN>(op.k, (double)x, (double)A, (double)B, out[0], out[1], out[2]);
+#pragma unroll
+            for (int e = 3; e < 8; ++e)
+                out[e] = 0.0;
+        }
+        if (active) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                acc[2 * e] += out[e];
+                acc[2 * e + 1] += out[e] * out[e];
+            }
+        }
+    }
+}
+
+template <class R, bool FT, bool ADJ>
+__global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchOption *__restrict__ opts,
+                                                      const uint32_t *__restrict__ item_opt,
+                                                      uint32_t item_begin, uint32_t item_end,
+                                                      uint32_t *counter,
+                                                      unsigned char *scratch,
+                                                      uint64_t scratch_per_block)
+{
+    __shared__ uint32_t s_item;
+    __shared__ double red[BLOCK / 64][N_ACC];
+    R *my_scratch = reinterpret_cast<R *>(scratch + (uint64_t)blockIdx.x * scratch_per_block);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t pos = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (pos >= item_end - item_begin)
+            break;
+        const uint32_t g = item_begin + pos;
+        const uint32_t o = __builtin_amdgcn_readfirstlane(item_opt[g]);
+        const BatchOption &op = opts[o];
+        const uint32_t i = g - op.first_item;
+        const uint64_t chunk = op.chunk_base + i;
+        double acc[N_ACC];
+#pragma unroll
+        for (int e = 0; e < N_ACC; ++e)
+            acc[e] = 0.0;
+        if (op.k.type >= 2)
+            run_item_paths<R, true, FT, ADJ>(op, chunk, my_scratch, acc);
+        else
+            run_item_paths<R, false, FT, ADJ>(op, chunk, my_scratch, acc);
+#pragma unroll
+        for (int e = 0; e < N_ACC; ++e) {
+            const double t = wave_sum(acc[e]);
+            if (lane == 0)
+                red[wave][e] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < N_ACC) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < BLOCK / 64; ++w)
+                t += red[w][threadIdx.x];
+            op.partials[(uint64_t)i * N_ACC + threadIdx.x] = t;
+        }
+    }
+}
+
+// Option o's sums: its items' partial records added in item order.  Thread t
+// owns column t % N_ACC and items i = t / N_ACC (mod BLOCK / N_ACC); the
+// BLOCK / N_ACC per-column partials are then added in a fixed order.
+__global__ __launch_bounds__(BLOCK) void batch_reduce_kernel(const BatchOption *__restrict__ opts,
+                                                             double *__restrict__ sums)
+{
+    constexpr int LANES = BLOCK / N_ACC;
+    __shared__ double red[LANES][N_ACC];
+    const BatchOption &op = opts[blockIdx.x];
+    const int col = threadIdx.x % N_ACC, slot = threadIdx.x / N_ACC;
+    double t = 0.0;
+    for (uint32_t i = slot; i < op.n_items; i += LANES)
+        t += op.partials[(uint64_t)i * N_ACC + col];
+    red[slot][col] = t;
+    __syncthreads();
+    if (threadIdx.x < N_ACC) {
+        double s = 0.0;
+        for (int k = 0; k < LANES; ++k)
+            s += red[k][threadIdx.x];
+        sums[(uint64_t)blockIdx.x * N_ACC + threadIdx.x] = s;
+    }
+}
+
+template <class R, bool FT, bool ADJ> int resident_blocks()
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<R, FT, ADJ>, BLOCK, 0) !=
+            hipSuccess)
+        return 0;
+    return cus * (per_cu > 0 ? per_cu : 1);
+}
+
+template <class R, bool FT, bool ADJ>
+hipError_t launch_t(const BatchLaunch &B, hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_kernel<R, FT, ADJ>), dim3(B.grid), dim3(BLOCK), 0, s, B.opts,
+                       B.item_opt, B.item_begin, B.item_end, B.counter, B.scratch,
+                       B.scratch_per_block);
+    return hipGetLastError();
+}
+
+template <class R, bool FT> int resident_r(bool adj)
+{
+    return adj ? resident_blocks<R, FT, true>() : resident_blocks<R, FT, false>();
+}
+
+template <class R, bool FT> hipError_t launch_r(const BatchLaunch &B, hipStream_t s)
+{
+    return B.adjoint ? launch_t<R, FT, true>(B, s) : launch_t<R, FT, false>(B, s);
+}
+
+} // namespace
+
+int batch_resident_blocks(int precision, int scheme, bool adjoint)
+{
+    if (precision == 0)
+        return scheme == 0 ? resident_r<double, true>(adjoint) : resident_r<double, false>(adjoint);
+    return scheme == 0 ? resident_r<float, true>(adjoint) : resident_r<float, false>(adjoint);
+}
+
+hipError_t launch_batch(const BatchLaunch &B, hipStream_t s)
+{
+    if (B.precision == 0)
+        return B.scheme == 0 ? launch_r<double, true>(B, s) : launch_r<double, false>(B, s);
+    return B.scheme == 0 ? launch_r<float, true>(B, s) : launch_r<float, false>(B, s);
+}
+
+hipError_t launch_batch_reduce(const BatchLaunch &B, double *sums, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(B.n_opts), dim3(BLOCK), 0, s, B.opts, sums);
+    return hipGetLastError();
+}
+
+} // namespace heston

@@ -73,6 +73,45 @@ struct PriceLaunch {
     uint32_t ckpt_every;            // steps between checkpoints
 };
 
+// Wave-uniform constants of one option's paths (single scenario).
+struct PathConsts {
+    StepCoef c;
+    double S0, K, r, T, v0, rho, rho_bar, sigma, theta;
+    uint64_t seed;
+    const uint32_t *fix_bits; // null: every step is a fixing date (Asian)
+    uint32_t n_steps, n_fix;
+    int type;                 // heston_option_type
+};
+
+// Batched launches: one option (request) of a batch and the launch itself.
+constexpr uint32_t BATCH_CHUNK = 1024;     // paths per work item (4 x BLOCK)
+constexpr int BATCH_CKPT_EVERY = 16;       // adjoint checkpoint interval in batches
+struct BatchOption {
+    PathConsts k;
+    uint64_t n_paths;
+    uint64_t chunk_base;      // chunk index of the option's first item in this launch
+    double *partials;         // device: record of item first_item + i at partials + i N_ACC
+    uint32_t first_item, n_items;
+    uint32_t adjoint; // 0: price + pathwise Delta/Rho; 1: price + 7 adjoint sensitivities
+    uint32_t pad;
+};
+struct BatchLaunch {
+    int precision, scheme;
+    bool adjoint;                // the items in [item_begin, item_end) are adjoint items
+    const BatchOption *opts;     // device [n_opts]
+    uint32_t n_opts;
+    const uint32_t *item_opt;    // device [n_items]
+    uint32_t item_begin, item_end;
+    uint32_t *counter;           // device, zero before the launch
+    unsigned char *scratch;      // device [grid][scratch_per_block] (adjoint checkpoints)
+    uint64_t scratch_per_block;
+    uint32_t grid;
+};
+int batch_resident_blocks(int precision, int scheme, bool adjoint);
+hipError_t launch_batch(const BatchLaunch &B, hipStream_t s);
+// sums[o][N_ACC]: option o's n_items records (at opts[o].partials) added in order.
+hipError_t launch_batch_reduce(const BatchLaunch &B, double *sums, hipStream_t s);
+
 // Checkpoint buffer of the adjoint, structure of arrays in the path state's
 // precision R: for c = 0 .. n_ckpt-1 the state at step c*every, x then V, each
 // [n_paths]; then the final log-price x_N and the fixing sum A = sum e^{x}

@@ -54,4 +54,193 @@ __device__ __forceinline__ void philox_normals(uint32_t j, uint32_t plo, uint32_
     }
 }
 
+__host__ __device__ inline PathConsts path_consts(const PriceLaunch &L)
+{
+    PathConsts k;
+    k.c = L.base;
+    k.S0 = L.S0;
+    k.K = L.K;
+    k.r = L.r;
+    k.T = L.T;
+    k.v0 = L.v0;
+    k.rho = L.rho;
+    k.rho_bar = L.rho_bar;
+    k.sigma = L.sigma;
+    k.theta = L.theta;
+    k.seed = L.seed;
+    k.fix_bits = L.fix_bits;
+    k.n_steps = L.n_steps;
+    k.n_fix = L.n_fix;
+    k.type = L.opt_type;
+    return k;
+}
+
+// One path's forward pass (single scenario): x_N, V_N, the fixing sums
+// A = sum e^x and B = sum t e^x; when ck is set, stores (x, V) before steps
+// 0, every, 2 every, ... and the final (x_N, A) in the checkpoint layout
+// with `stride` paths per row.
+template <class R, bool ASIAN, bool FT>
+__device__ __forceinline__ void forward_path(const PathConsts &k, uint64_t p, R &x, R &v, R &A,
+                                             R &B, R *ck, uint64_t stride, uint64_t row,
+                                             uint32_t every)
+{
+    const Coef<R> c = coef<R>(k.c);
+    const R rho = (R)k.rho, rho_bar = (R)k.rho_bar, sigma = (R)k.sigma;
+    const uint32_t k0 = (uint32_t)k.seed, k1 = (uint32_t)(k.seed >> 32);
+    const uint32_t plo = (uint32_t)p, phi = (uint32_t)(p >> 32);
+    const uint32_t N = k.n_steps;
+    x = R(0);
+    v = (R)k.v0;
+    A = R(0);
+    B = R(0);
+    auto step = [&](uint32_t j, R za, R zb) {
+        const R z2 = rho * za + rho_bar * zb;
+        mil_step<R, FT>(x, v, c, za, sigma * z2, c.qdt * (z2 * z2 - R(1)));
+        if constexpr (ASIAN) {
+            if (is_fixing(k.fix_bits, j + 1)) {
+                const R e = fast_exp(x);
+                A += e;
+                B += (R)(j + 1) * c.dt * e;
+            }
+        }
+    };
+    for (uint32_t j = 0; j < N; j += 2) {
+        if (ck != nullptr && j % every == 0) {
+            const uint64_t cc = j / every;
+            ck[(2 * cc) * stride + row] = x;
+            ck[(2 * cc + 1) * stride + row] = v;
+        }
+        R za0, zb0, za1, zb1;
+        philox_normals<R>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
+        step(j, za0, zb0);
+        if (j + 1 < N)
+            step(j + 1, za1, zb1);
+    }
+    if (ck != nullptr) {
+        const uint64_t cc = ckpt_count(N, every);
+        ck[(2 * cc) * stride + row] = x;
+        ck[(2 * cc + 1) * stride + row] = A;
+    }
+}
+
+// Discounted payoff and the paper's pathwise Delta / Rho of one path, in FP64.
+template <bool ASIAN>
+__device__ __forceinline__ void path_estimators(const PathConsts &k, double x, double A, double B,
+                                                double &pay, double &pw_delta, double &pw_rho)
+{
+    const double D = exp(-k.r * k.T);
+    const double inv_nfix = 1.0 / (double)k.n_fix;
+    const double rel = ASIAN ? A * inv_nfix : exp(x);
+    const double X = k.S0 * rel;
+    const bool call = k.type == 0 || k.type == 2;
+    const double sgn = call ? 1.0 : -1.0;
+    const double in = sgn * (X - k.K);
+    const bool itm = in > 0.0;
+    pay = itm ? D * in : 0.0;
+    pw_delta = itm ? sgn * D * rel : 0.0;
+    if (ASIAN)
+        pw_rho = itm ? D * (sgn * k.S0 * B * inv_nfix - k.T * in) : 0.0;
+    else
+        pw_rho = itm ? sgn * D * k.K * k.T : 0.0;
+}
+
+// Reverse sweep of one path over its checkpoints (see adjoint_kernel.hip):
+// out = (payoff, d/dS0, d/dv0, d/dr, d/dkappa, d/dtheta, d/dsigma, d/drho).
+template <class R, bool ASIAN, bool FT, int SEG>
+__device__ __forceinline__ void adjoint_path(const PathConsts &k, uint64_t p, const R *ck,
+                                             uint64_t stride, uint64_t row, double out[8])
+{
+    const uint32_t N = k.n_steps;
+    const uint64_t nck = ckpt_count(N, SEG);
+    const Coef<R> c = coef<R>(k.c);
+    const R rho = (R)k.rho, rho_bar = (R)k.rho_bar, sigma = (R)k.sigma, theta = (R)k.theta;
+    const R rho_ratio = (R)(k.rho_bar > 0 ? k.rho / k.rho_bar : 0.0); // -d rho_bar / d rho
+    const R half_sigma_dt = (R)(0.5 * k.sigma * k.c.dt);              // d(qdt)/d sigma
+    const R two_qdt = (R)(2.0 * k.c.quarter_sigma2_dt);
+    const uint32_t k0 = (uint32_t)k.seed, k1 = (uint32_t)(k.seed >> 32);
+    const uint32_t plo = (uint32_t)p, phi = (uint32_t)(p >> 32);
+
+    // payoff and its seeds (FP64, as in the pricing epilogue)
+    const double S0 = k.S0, D = exp(-k.r * k.T), inv_nfix = 1.0 / (double)k.n_fix;
+    const R xN = ck[(2 * nck) * stride + row];
+    const R AN = ck[(2 * nck + 1) * stride + row];
+    const double rel = ASIAN ? (double)AN * inv_nfix : exp((double)xN);
+    const double X = S0 * rel;
+    const bool call = k.type == 0 || k.type == 2;
+    const double sgn = call ? 1.0 : -1.0;
+    const double in = sgn * (X - k.K);
+    const bool itm = in > 0.0;
+    const double y = itm ? D * in : 0.0;
+    const double g_S0 = itm ? sgn * D * rel : 0.0;
+    const R c_fix = (R)(itm ? sgn * D * S0 * inv_nfix : 0.0); // dy / d e^{x_i} at a fixing
+
+    R xbar = (!ASIAN && itm) ? (R)(sgn * D * X) : R(0); // dy/dx_N for a European
+    R vbar = 0, sum_xbar = 0, kbar = 0, thbar = 0, sbar = 0, rhobar = 0;
+
+    for (int64_t seg = (int64_t)nck - 1; seg >= 0; --seg) {
+        const uint32_t s0 = (uint32_t)seg * SEG;
+        const uint32_t len = N - s0 < (uint32_t)SEG ? N - s0 : (uint32_t)SEG;
+        R x = ck[(2 * (uint64_t)seg) * stride + row];
+        R v = ck[(2 * (uint64_t)seg + 1) * stride + row];
+        R a_vp[SEG], a_s[SEG], a_za[SEG], a_zb[SEG], a_f[SEG];
+        bool a_clip[SEG];
+        // forward recomputation of the segment
+#pragma unroll
+        for (int q = 0; q < SEG; q += 2) {
+            if ((uint32_t)q < len) {
+                R za[2], zb[2];
+                philox_normals<R>(s0 + q, plo, phi, k0, k1, za[0], zb[0], za[1], zb[1]);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int qq = q + h;
+                    if ((uint32_t)qq < len) {
+                        const R z2 = rho * za[h] + rho_bar * zb[h];
+                        const R vp = v > R(0) ? v : R(0);
+                        a_vp[qq] = vp;
+                        a_s[qq] = fast_sqrt(vp * c.dt);
+                        a_za[qq] = za[h];
+                        a_zb[qq] = zb[h];
+                        const R vb = FT ? v : vp;
+                        const R vpre = vb + (c.ktdt - c.kdt * vp) + (sigma * z2) * a_s[qq] +
+                                       c.qdt * (z2 * z2 - R(1));
+                        mil_step<R, FT>(x, v, c, za[h], sigma * z2, c.qdt * (z2 * z2 - R(1)));
+                        a_clip[qq] = !FT && !(vpre > R(0));
+                        a_f[qq] = (ASIAN && is_fixing(k.fix_bits, s0 + qq + 1)) ? c_fix * fast_exp(x)
+                                                                               : R(0);
+                    }
+                }
+            }
+        }
+        // reverse sweep
+#pragma unroll
+        for (int q = SEG - 1; q >= 0; --q) {
+            if ((uint32_t)q < len) {
+                xbar += a_f[q]; // now the adjoint of x_{j+1}
+                if (!FT && a_clip[q])
+                    vbar = R(0); // V_{j+1} = max(pre, 0) with pre <= 0
+                sum_xbar += xbar;
+                const R vp = a_vp[q], s = a_s[q], za = a_za[q], zb = a_zb[q];
+                const R z2 = rho * za + rho_bar * zb;
+                const R dz2 = za - rho_ratio * zb;
+                const bool pos = vp > R(0);
+                const R dsdv = pos ? c.half_dt / s : R(0);
+                const R g = xbar * (za * dsdv - c.half_dt) + vbar * (sigma * z2 * dsdv - c.kdt);
+                kbar += vbar * (theta - vp);
+                thbar += vbar;
+                sbar += vbar * (s * z2 + half_sigma_dt * (z2 * z2 - R(1)));
+                rhobar += vbar * (sigma * s + two_qdt * z2) * dz2;
+                vbar = FT ? vbar + (pos ? g : R(0)) : (pos ? vbar + g : R(0));
+            }
+        }
+    }
+    out[0] = y;
+    out[1] = g_S0;
+    out[2] = (double)vbar;
+    out[3] = (double)sum_xbar * k.c.dt - k.T * y;
+    out[4] = (double)kbar * k.c.dt;
+    out[5] = (double)thbar * k.c.kappa_dt;
+    out[6] = (double)sbar;
+    out[7] = (double)rhobar;
+}
+
 } // namespace heston
