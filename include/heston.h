@@ -307,7 +307,7 @@ typedef struct heston_server_config {
     uint32_t reserved;
     uint64_t hbm_budget_bytes;  /* device memory for request state and launch
                                    buffers (default 8 GiB)                        */
-    uint64_t launch_path_steps; /* work per launch (default 2^31 path-steps)      */
+    uint64_t launch_path_steps; /* work per launch (default 2^29 path-steps)      */
 } heston_server_config;
 
 typedef struct heston_server_stats {

@@ -18,6 +18,45 @@
 namespace heston {
 namespace {
 
+// The forward pass of the adjoint: one path per lane, checkpoints of (x, V)
+// every `every` steps and the final (x_N, A), then the payoff and pathwise
+// estimators into FP64 block partials (price, Delta, Rho in the N_ACC layout).
+template <class R, bool ASIAN, bool FT>
+__global__ __launch_bounds__(BLOCK) void adjoint_forward_kernel(const PriceLaunch L)
+{
+    __shared__ double red[BLOCK / 64][N_ACC];
+    const uint64_t np = L.n_paths;
+    const uint64_t row = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const bool active = row < np;
+    const uint64_t rr = active ? row : 0;
+    const PathConsts k = path_consts(L);
+    R x, v, A, B;
+    R *ck = reinterpret_cast<R *>(L.ckpt);
+    forward_path<R, ASIAN, FT>(k, L.first_path + rr, x, v, A, B, active ? ck : nullptr, np, rr,
+                               L.ckpt_every);
+    double out[3];
+    path_estimators<ASIAN>(k, (double)x, (double)A, (double)B, out[0], out[1], out[2]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int e = 0; e < N_EST; ++e) {
+        const double ye = (active && e < 3) ? out[e < 3 ? e : 0] : 0.0;
+        const double s1 = wave_sum(ye);
+        const double s2 = wave_sum(ye * ye);
+        if (lane == 0) {
+            red[wave][2 * e] = s1;
+            red[wave][2 * e + 1] = s2;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < N_ACC) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w)
+            t += red[w][threadIdx.x];
+        L.partials[(uint64_t)blockIdx.x * N_ACC + threadIdx.x] = t;
+    }
+}
+
 template <class R, bool ASIAN, bool FT, int SEG>
 __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const PriceLaunch L, double seed_grad,
                                                         double *__restrict__ per_path)
@@ -82,7 +121,31 @@ hipError_t launch_r(const PriceLaunch &L, double g, double *pp, hipStream_t s)
                          : launch_seg<R, false, false>(L, g, pp, s);
 }
 
+template <class R>
+hipError_t launch_fwd_r(const PriceLaunch &L, hipStream_t s)
+{
+    const dim3 grid((uint32_t)((L.n_paths + BLOCK - 1) / BLOCK));
+    const bool asian = L.opt_type >= 2;
+    if (asian) {
+        if (L.scheme == 0)
+            hipLaunchKernelGGL((adjoint_forward_kernel<R, true, true>), grid, dim3(BLOCK), 0, s, L);
+        else
+            hipLaunchKernelGGL((adjoint_forward_kernel<R, true, false>), grid, dim3(BLOCK), 0, s, L);
+    } else {
+        if (L.scheme == 0)
+            hipLaunchKernelGGL((adjoint_forward_kernel<R, false, true>), grid, dim3(BLOCK), 0, s, L);
+        else
+            hipLaunchKernelGGL((adjoint_forward_kernel<R, false, false>), grid, dim3(BLOCK), 0, s, L);
+    }
+    return hipGetLastError();
+}
+
 } // namespace
+
+hipError_t launch_adjoint_forward(const PriceLaunch &L, hipStream_t stream)
+{
+    return L.precision == 0 ? launch_fwd_r<double>(L, stream) : launch_fwd_r<float>(L, stream);
+}
 
 hipError_t launch_adjoint(const PriceLaunch &L, double seed_grad, double *per_path,
                           hipStream_t stream)

@@ -232,6 +232,7 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
     L.seed = q.seed;
     L.first_path = first;
     L.n_paths = count;
+    L.wide_paths = first + count > (1ull << 32);
     L.base = step_coef(p, p.T, q.n_steps);
     if (L.bumps) {
         L.hS = o.bump_S0_rel * p.S0;
@@ -254,7 +255,16 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
             return st;
         HIP_TRY(hipMemcpyAsync(c->fix_bits.ptr, bits.data(), words * 4, hipMemcpyHostToDevice,
                                c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream)); // `bits` is released at return
         L.fix_bits = (const uint32_t *)c->fix_bits.ptr;
+    }
+    if (asian) {
+        const size_t real = o.precision == HESTON_FP64 ? 8 : 4;
+        heston_status st = reserve(c, c->step_w, (size_t)q.n_steps * STEP_WEIGHTS * real);
+        if (st != HESTON_OK)
+            return st;
+        L.step_weights = c->step_w.ptr;
+        HIP_TRY(launch_step_weights(L, c->step_w.ptr, c->stream));
     }
     uint64_t M;
     if (o.rng == HESTON_RNG_SOBOL_BRIDGE) {
@@ -433,7 +443,7 @@ heston_status bump_revalue_impl(heston_ctx *c, const Request &q0, const heston_b
                                    c->stream));
         }
     }
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, 2048);
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, 1024);
     if ((st = reserve(c, c->bump_partials, (size_t)blocks * BUMP_W * 8)) != HESTON_OK ||
         (st = reserve(c, c->bump_sums, BUMP_W * 8)) != HESTON_OK)
         return st;
@@ -539,7 +549,7 @@ heston_status heston_ctx_destroy(heston_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift,
                       &c->bridge_start, &c->bridge_ops, &c->pay, &c->bump_partials,
-                      &c->bump_sums, &c->batch_opts, &c->batch_items, &c->batch_partials,
+                      &c->bump_sums, &c->step_w, &c->batch_opts, &c->batch_items, &c->batch_partials,
                       &c->batch_sums, &c->batch_counter, &c->batch_scratch})
         if (b->ptr)
             (void)hipFree(b->ptr);
@@ -711,7 +721,7 @@ heston_status heston_adjoint_forward(heston_ctx *c, const heston_params *params,
     L.ckpt = ckpt_dev;
     L.ckpt_every = every;
     HIP_TRY(hipEventRecord(c->ev0, c->stream));
-    HIP_TRY(launch_paths(L, c->stream));
+    HIP_TRY(launch_adjoint_forward(L, c->stream));
     HIP_TRY(hipEventRecord(c->ev1, c->stream));
     HIP_TRY(launch_reduce(L, (double *)c->rep_sums.ptr, c->stream));
     HIP_TRY(hipMemcpyAsync(c->host_sums, c->rep_sums.ptr, N_ACC * 8, hipMemcpyDeviceToHost,

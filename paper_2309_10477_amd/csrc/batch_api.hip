@@ -54,6 +54,7 @@ BatchOption batch_option(const heston_request &r)
     k.n_steps = r.n_steps;
     k.n_fix = r.type >= 2 ? r.n_steps : 1;
     k.type = r.type;
+    k.wide = r.n_paths > (1ull << 32) ? 1u : 0u;
     b.n_paths = r.n_paths;
     b.adjoint = r.want == HESTON_WANT_ADJOINT ? 1u : 0u;
     return b;

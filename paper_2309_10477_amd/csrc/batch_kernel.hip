@@ -22,11 +22,14 @@
 namespace heston {
 namespace {
 
+// Runs the item's BATCH_CHUNK paths, 256 at a time; after each sub-block the
+// wave's sums are added to its LDS row red[wave] (FP64, sub-block order).
 template <class R, bool ASIAN, bool FT, bool ADJ>
 __device__ __forceinline__ void run_item_paths(const BatchOption &op, uint64_t chunk, R *scratch,
-                                               double acc[N_ACC])
+                                               double (*red)[N_ACC])
 {
     const uint32_t tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll 1
     for (uint32_t sub = 0; sub < BATCH_CHUNK / BLOCK; ++sub) {
         const uint64_t p = chunk * BATCH_CHUNK + (uint64_t)sub * BLOCK + tid;
@@ -45,11 +48,14 @@ __device__ __forceinline__ void run_item_paths(const BatchOption &op, uint64_t c
             for (int e = 3; e < 8; ++e)
                 out[e] = 0.0;
         }
-        if (active) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                acc[2 * e] += out[e];
-                acc[2 * e + 1] += out[e] * out[e];
+        for (int e = 0; e < 8; ++e) {
+            const double y = active ? out[e] : 0.0;
+            const double s1 = wave_sum(y);
+            const double s2 = wave_sum(y * y);
+            if (lane == 0) {
+                red[wave][2 * e] += s1;
+                red[wave][2 * e + 1] += s2;
             }
         }
     }
@@ -80,20 +86,12 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchOption *__restr
         const BatchOption &op = opts[o];
         const uint32_t i = g - op.first_item;
         const uint64_t chunk = op.chunk_base + i;
-        double acc[N_ACC];
-#pragma unroll
-        for (int e = 0; e < N_ACC; ++e)
-            acc[e] = 0.0;
+        if (lane < N_ACC)
+            red[wave][lane] = 0.0;
         if (op.k.type >= 2)
-            run_item_paths<R, true, FT, ADJ>(op, chunk, my_scratch, acc);
+            run_item_paths<R, true, FT, ADJ>(op, chunk, my_scratch, red);
         else
-            run_item_paths<R, false, FT, ADJ>(op, chunk, my_scratch, acc);
-#pragma unroll
-        for (int e = 0; e < N_ACC; ++e) {
-            const double t = wave_sum(acc[e]);
-            if (lane == 0)
-                red[wave][e] = t;
-        }
+            run_item_paths<R, false, FT, ADJ>(op, chunk, my_scratch, red);
         __syncthreads();
         if (threadIdx.x < N_ACC) {
             double t = 0.0;

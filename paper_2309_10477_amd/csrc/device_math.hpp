@@ -64,13 +64,36 @@ __device__ __forceinline__ void box_muller(double ua, double ub, double &za, dou
     zb = rad * s;
 }
 
-// Inverse standard normal CDF (device math library).
-__device__ __forceinline__ float inv_normal(float u) { return normcdfinvf(u); }
-__device__ __forceinline__ double inv_normal(double u) { return normcdfinv(u); }
+// Inverse standard normal CDF on the lower half, u in [2^-31, 1/2].
+// Single precision: Wichura's algorithm AS 241 (Applied Statistics 37, 1988),
+// its single-precision form PPND7 (relative accuracy about 1e-7), evaluated
+// branch-free: the central rational in r = 0.180625 - q^2, q = u - 1/2, for
+// u >= 0.075 and the first tail rational in t = sqrt(-ln u) - 1.6 below, both
+// computed and one selected.  All coefficients are positive and r, t >= 0 on
+// their ranges, so neither polynomial cancels in binary32.  The second tail
+// (sqrt(-ln u) > 5, u < 1.4e-11) lies outside the stated domain.
+// Double precision: the device math library's normcdfinv.
+__device__ __forceinline__ float inv_normal_lower(float u)
+{
+    const float q = u - 0.5f, r = 0.180625f - q * q;
+    const float num_c = ((59.109374720f * r + 159.29113202f) * r + 50.434271938f) * r + 3.3871327179f;
+    const float den_c = ((67.187563600f * r + 78.757757664f) * r + 17.895169469f) * r + 1.0f;
+    const float zc = q * num_c * __builtin_amdgcn_rcpf(den_c);
+    // -ln u = -ln2 log2 u
+    const float t =
+        __builtin_amdgcn_sqrtf(-0.69314718055994530942f * __builtin_amdgcn_logf(u)) - 1.6f;
+    const float num_t = ((0.17023821103f * t + 1.3067284816f) * t + 2.7568153900f) * t + 1.4234372777f;
+    const float den_t = (0.12021132975f * t + 0.73700164250f) * t + 1.0f;
+    const float zt = -num_t * __builtin_amdgcn_rcpf(den_t);
+    return u < 0.075f ? zt : zc;
+}
+__device__ __forceinline__ double inv_normal_lower(double u) { return normcdfinv(u); }
 
 // Real-typed helpers.
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float fast_exp(float x)
 {
     return __builtin_amdgcn_exp2f(x * 1.44269504088896340736f);

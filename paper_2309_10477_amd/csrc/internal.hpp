@@ -23,6 +23,9 @@ constexpr int N_ACC = 2 * N_EST;   // doubles per partial record
 constexpr int DUMP_WIDTH = 16;
 constexpr int BLOCK = 256;         // threads per block of the path kernels
 constexpr int MAX_BRIDGE_DEPTH = 24;
+// Fixing weights per step j (fixing time t = (j+1) dt): e^{rt}, t e^{rt},
+// t^2 e^{rt}, t^3 e^{rt} on the base grid, e^{rt} on the T + hT and T - hT grids.
+constexpr int STEP_WEIGHTS = 8;
 
 // Step coefficients of one time grid (dt = T/N of a scenario), computed once
 // on the host in FP64.
@@ -52,6 +55,7 @@ struct PriceLaunch {
     uint64_t first_path;            // first path handled by the launch
     uint64_t n_paths;               // paths in the launch
     uint64_t paths_per_rep;         // points per replicate (Sobol), n_paths for Philox
+    bool wide_paths;                // some path index of the launch is >= 2^32
     uint32_t n_reps;                // replicates covered by the launch
     uint32_t rep0;                  // replicate of the launch's first path
     // bumps
@@ -69,6 +73,7 @@ struct PriceLaunch {
     uint32_t blocks_per_rep;
     double *dump;                   // device [n_paths][DUMP_WIDTH] or null
     double *pay_out;                // device [n_paths] discounted payoff per path, or null
+    const void *step_weights;       // device [N][STEP_WEIGHTS] in the path precision (Asian)
     void *ckpt;                     // device checkpoint buffer (adjoint forward) or null
     uint32_t ckpt_every;            // steps between checkpoints
 };
@@ -81,11 +86,12 @@ struct PathConsts {
     const uint32_t *fix_bits; // null: every step is a fixing date (Asian)
     uint32_t n_steps, n_fix;
     int type;                 // heston_option_type
+    uint32_t wide;            // some path index is >= 2^32
 };
 
 // Batched launches: one option (request) of a batch and the launch itself.
 constexpr uint32_t BATCH_CHUNK = 1024;     // paths per work item (4 x BLOCK)
-constexpr int BATCH_CKPT_EVERY = 16;       // adjoint checkpoint interval in batches
+constexpr int BATCH_CKPT_EVERY = 8;        // adjoint checkpoint interval in batches
 struct BatchOption {
     PathConsts k;
     uint64_t n_paths;
@@ -125,6 +131,11 @@ inline uint64_t ckpt_bytes(uint64_t n_paths, uint32_t n_steps, uint32_t every, s
     return (2 * ckpt_count(n_steps, every) + 2) * n_paths * real;
 }
 
+// Adjoint forward: prices the request's paths and stores the checkpoints of
+// L.ckpt every L.ckpt_every steps; block partials of (price, pathwise Delta,
+// pathwise Rho) in L.partials as for launch_paths.
+hipError_t launch_adjoint_forward(const PriceLaunch &L, hipStream_t stream);
+
 // Adjoint sums: price and the derivatives of the discounted payoff with respect
 // to (S0, v0, r, kappa, theta, sigma, rho), each as (sum, sum of squares).
 enum AdjointOut : int { ADJ_PRICE = 0, ADJ_S0, ADJ_V0, ADJ_R, ADJ_KAPPA, ADJ_THETA, ADJ_SIGMA, ADJ_RHO };
@@ -159,6 +170,10 @@ hipError_t launch_paths(const PriceLaunch &L, hipStream_t stream);
 // Sums the partial records of each replicate, in a fixed order, into
 // `rep_sums` (device [n_reps][N_ACC]).
 hipError_t launch_reduce(const PriceLaunch &L, double *rep_sums, hipStream_t stream);
+
+// Fills the [N][STEP_WEIGHTS] fixing weights of `L` (its precision) at
+// L.step_weights.
+hipError_t launch_step_weights(const PriceLaunch &L, void *out, hipStream_t stream);
 
 // Writes the [reps][dims] digital shifts of the Sobol replicates of `seed`.
 hipError_t launch_sobol_shifts(uint64_t seed, uint32_t dims, uint32_t reps, uint32_t *out,

@@ -72,6 +72,7 @@ __host__ __device__ inline PathConsts path_consts(const PriceLaunch &L)
     k.n_steps = L.n_steps;
     k.n_fix = L.n_fix;
     k.type = L.opt_type;
+    k.wide = L.wide_paths ? 1u : 0u;
     return k;
 }
 
@@ -87,7 +88,7 @@ __device__ __forceinline__ void forward_path(const PathConsts &k, uint64_t p, R 
     const Coef<R> c = coef<R>(k.c);
     const R rho = (R)k.rho, rho_bar = (R)k.rho_bar, sigma = (R)k.sigma;
     const uint32_t k0 = (uint32_t)k.seed, k1 = (uint32_t)(k.seed >> 32);
-    const uint32_t plo = (uint32_t)p, phi = (uint32_t)(p >> 32);
+    const uint32_t plo = (uint32_t)p, phi = k.wide ? (uint32_t)(p >> 32) : 0u;
     const uint32_t N = k.n_steps;
     x = R(0);
     v = (R)k.v0;
@@ -158,7 +159,7 @@ __device__ __forceinline__ void adjoint_path(const PathConsts &k, uint64_t p, co
     const R half_sigma_dt = (R)(0.5 * k.sigma * k.c.dt);              // d(qdt)/d sigma
     const R two_qdt = (R)(2.0 * k.c.quarter_sigma2_dt);
     const uint32_t k0 = (uint32_t)k.seed, k1 = (uint32_t)(k.seed >> 32);
-    const uint32_t plo = (uint32_t)p, phi = (uint32_t)(p >> 32);
+    const uint32_t plo = (uint32_t)p, phi = k.wide ? (uint32_t)(p >> 32) : 0u;
 
     // payoff and its seeds (FP64, as in the pricing epilogue)
     const double S0 = k.S0, D = exp(-k.r * k.T), inv_nfix = 1.0 / (double)k.n_fix;
@@ -182,7 +183,7 @@ __device__ __forceinline__ void adjoint_path(const PathConsts &k, uint64_t p, co
         const uint32_t len = N - s0 < (uint32_t)SEG ? N - s0 : (uint32_t)SEG;
         R x = ck[(2 * (uint64_t)seg) * stride + row];
         R v = ck[(2 * (uint64_t)seg + 1) * stride + row];
-        R a_vp[SEG], a_s[SEG], a_za[SEG], a_zb[SEG], a_f[SEG];
+        R a_vp[SEG], a_za[SEG], a_zb[SEG], a_f[SEG];
         bool a_clip[SEG];
         // forward recomputation of the segment
 #pragma unroll
@@ -197,11 +198,10 @@ __device__ __forceinline__ void adjoint_path(const PathConsts &k, uint64_t p, co
                         const R z2 = rho * za[h] + rho_bar * zb[h];
                         const R vp = v > R(0) ? v : R(0);
                         a_vp[qq] = vp;
-                        a_s[qq] = fast_sqrt(vp * c.dt);
                         a_za[qq] = za[h];
                         a_zb[qq] = zb[h];
                         const R vb = FT ? v : vp;
-                        const R vpre = vb + (c.ktdt - c.kdt * vp) + (sigma * z2) * a_s[qq] +
+                        const R vpre = vb + (c.ktdt - c.kdt * vp) + (sigma * z2) * fast_sqrt(vp * c.dt) +
                                        c.qdt * (z2 * z2 - R(1));
                         mil_step<R, FT>(x, v, c, za[h], sigma * z2, c.qdt * (z2 * z2 - R(1)));
                         a_clip[qq] = !FT && !(vpre > R(0));
@@ -219,11 +219,15 @@ __device__ __forceinline__ void adjoint_path(const PathConsts &k, uint64_t p, co
                 if (!FT && a_clip[q])
                     vbar = R(0); // V_{j+1} = max(pre, 0) with pre <= 0
                 sum_xbar += xbar;
-                const R vp = a_vp[q], s = a_s[q], za = a_za[q], zb = a_zb[q];
+                const R vp = a_vp[q], za = a_za[q], zb = a_zb[q];
                 const R z2 = rho * za + rho_bar * zb;
                 const R dz2 = za - rho_ratio * zb;
                 const bool pos = vp > R(0);
-                const R dsdv = pos ? c.half_dt / s : R(0);
+                // s = sqrt(V+ dt) and ds/dV+ = dt / (2 s) from one reciprocal square root
+                const R s2 = vp * c.dt;
+                const R rs = pos ? fast_rsqrt(s2) : R(0);
+                const R s = s2 * rs;
+                const R dsdv = c.half_dt * rs;
                 const R g = xbar * (za * dsdv - c.half_dt) + vbar * (sigma * z2 * dsdv - c.kdt);
                 kbar += vbar * (theta - vp);
                 thbar += vbar;

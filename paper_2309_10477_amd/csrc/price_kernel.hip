@@ -54,8 +54,64 @@ template <class R> __device__ __forceinline__ R sobol_normal(uint32_t x)
 {
     const bool upper = x >= (1u << 29);
     const uint32_t xs = upper ? 0x3FFFFFFFu - x : x;
-    const R z = inv_normal(((R)xs + R(0.5)) * R(0x1p-30));
+    const R z = inv_normal_lower(((R)xs + R(0.5)) * R(0x1p-30));
     return upper ? -z : z;
+}
+
+// The low six Gray-code bits of a lane's point select direction numbers
+// v[0..5]; `m` holds all-ones or zero masks for them.
+__device__ __forceinline__ uint32_t sobol_low(const uint32_t *__restrict__ v, const uint32_t m[6])
+{
+    return (m[0] & v[0]) ^ (m[1] & v[1]) ^ (m[2] & v[2]) ^ (m[3] & v[3]) ^ (m[4] & v[4]) ^
+           (m[5] & v[5]);
+}
+
+// The fused kernel carries each scenario's state scaled: y = ln(S/S0) / ln 2,
+// so the fixing exponential is a single exp2, and w = V dt, so the diffusion
+// coefficient is sqrt(w+); the constants of each time grid absorb the scales.
+// Per step and scenario this is the same Milstein step (paper: algorithm
+// "Milstein approximation under Heston model") multiplied through by 1/ln 2
+// and by dt respectively.
+constexpr double LOG2E = 1.4426950408889634074;
+constexpr double LN2 = 0.69314718055994530942;
+
+template <class R> struct Grid {
+    R kdt;   // kappa dt
+    R ktdt2; // kappa theta dt^2
+    R qdt2;  // sigma^2 dt^2 / 4
+    R sdt;   // sigma dt
+    R dt;
+};
+
+template <class R> __device__ __forceinline__ Grid<R> grid(const StepCoef &c, double sigma)
+{
+    return Grid<R>{(R)c.kappa_dt, (R)(c.kappa_theta_dt * c.dt), (R)(c.quarter_sigma2_dt * c.dt),
+                   (R)(sigma * c.dt), (R)c.dt};
+}
+
+// max(w, 0) as one v_med3 (no NaN canonicalisation of the loop-carried w).
+__device__ __forceinline__ float clamp0(float w) { return __builtin_amdgcn_fmed3f(w, 0.0f, 3.0e38f); }
+__device__ __forceinline__ double clamp0(double w) { return w > 0.0 ? w : 0.0; }
+__device__ __forceinline__ float exp2r(float y) { return __builtin_amdgcn_exp2f(y); }
+__device__ __forceinline__ double exp2r(double y) { return exp2(y); }
+
+// One scaled step on grid g; z1l = Z1 / ln 2, a_g = kappa theta dt^2 +
+// sigma^2 dt^2 (Z2^2 - 1) / 4, s_g = sigma dt Z2.  y leaves out the
+// deterministic drift r t / ln 2, which is added back where S is needed: at
+// the end of the path, and at a fixing date through the weight e^{r t_j}.
+template <class R, bool FT>
+__device__ __forceinline__ void scaled_step(R &y, R &w, const Grid<R> &g, R z1l, R a_g, R s_g)
+{
+    constexpr R HALF_LOG2E = (R)(0.5 * LOG2E);
+    const R vp = clamp0(w);
+    const R s = fast_sqrt(vp);
+    y = y - HALF_LOG2E * vp;
+    y = y + s * z1l;
+    const R wb = FT ? w : vp;
+    w = wb + (a_g - g.kdt * vp);
+    w = w + s * s_g;
+    if (!FT)
+        w = clamp0(w);
 }
 
 template <class R, int RNG, bool ASIAN, bool BUMPS, bool FT>
@@ -74,51 +130,49 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
     const bool active = p < hi;
 
     const uint32_t N = L.n_steps;
-    const Coef<R> cb = coef<R>(L.base);
-    const R rho = (R)L.rho, rho_bar = (R)L.rho_bar, sigma = (R)L.sigma;
+    const Grid<R> gb = grid<R>(L.base, L.sigma);
+    const R rho = (R)L.rho, rho_bar = (R)L.rho_bar, log2e = (R)LOG2E;
 
-    R x = 0, v = (R)L.v0, A = 0, B = 0, C = 0, D3 = 0;
+    R y = 0, w = (R)(L.v0 * L.base.dt), A = 0, B = 0, C = 0, D3 = 0;
     // bump scenarios that need their own paths: v0 +/- and T +/-
-    Coef<R> cu{}, cd{};
-    R xv0 = 0, xv1 = 0, vv0 = (R)(L.v0 + L.hv), vv1 = (R)(L.v0 - L.hv), Av0 = 0, Av1 = 0;
-    R xt0 = 0, xt1 = 0, vt0 = (R)L.v0, vt1 = (R)L.v0, At0 = 0, At1 = 0;
+    Grid<R> gu{}, gd{};
+    R yv0 = 0, yv1 = 0, wv0 = (R)((L.v0 + L.hv) * L.base.dt), wv1 = (R)((L.v0 - L.hv) * L.base.dt);
+    R yt0 = 0, yt1 = 0, wt0 = (R)(L.v0 * L.tup.dt), wt1 = (R)(L.v0 * L.tdn.dt);
+    R Av0 = 0, Av1 = 0, At0 = 0, At1 = 0;
     if constexpr (BUMPS) {
-        cu = coef<R>(L.tup);
-        cd = coef<R>(L.tdn);
+        gu = grid<R>(L.tup, L.sigma);
+        gd = grid<R>(L.tdn, L.sigma);
     }
 
     // One step given the independent normals (za, zb) of step j.
     auto step = [&](uint32_t j, R za, R zb) {
-        const R z1 = za;
+        const R z1l = za * log2e;
         const R z2 = rho * za + rho_bar * zb;
-        const R sz2 = sigma * z2;
         const R z2m1 = z2 * z2 - R(1);
-        mil_step<R, FT>(x, v, cb, z1, sz2, cb.qdt * z2m1);
+        const R ab = gb.ktdt2 + gb.qdt2 * z2m1, sb = gb.sdt * z2;
+        scaled_step<R, FT>(y, w, gb, z1l, ab, sb);
         if constexpr (BUMPS) {
-            const R mb = cb.qdt * z2m1;
-            mil_step<R, FT>(xv0, vv0, cb, z1, sz2, mb);
-            mil_step<R, FT>(xv1, vv1, cb, z1, sz2, mb);
-            mil_step<R, FT>(xt0, vt0, cu, z1, sz2, cu.qdt * z2m1);
-            mil_step<R, FT>(xt1, vt1, cd, z1, sz2, cd.qdt * z2m1);
+            scaled_step<R, FT>(yv0, wv0, gb, z1l, ab, sb);
+            scaled_step<R, FT>(yv1, wv1, gb, z1l, ab, sb);
+            scaled_step<R, FT>(yt0, wt0, gu, z1l, gu.ktdt2 + gu.qdt2 * z2m1, gu.sdt * z2);
+            scaled_step<R, FT>(yt1, wt1, gd, z1l, gd.ktdt2 + gd.qdt2 * z2m1, gd.sdt * z2);
         }
         if constexpr (ASIAN) {
-            const uint32_t jf = j + 1;
-            const bool fix = is_fixing(L.fix_bits, jf);
-            if (fix) {
-                const R e = fast_exp(x);
-                const R t = (R)jf * cb.dt;
-                A += e;
-                const R te = t * e;
-                B += te;
+            if (is_fixing(L.fix_bits, j + 1)) {
+                // weights of the fixing at t = (j+1) dt: e^{rt}, t e^{rt}, t^2 e^{rt},
+                // t^3 e^{rt} (base grid), e^{rt} on the T +/- grids
+                const R *tw = reinterpret_cast<const R *>(L.step_weights) + STEP_WEIGHTS * j;
+                const R e = exp2r(y);
+                A += tw[0] * e;
+                B += tw[1] * e;
                 if constexpr (BUMPS) {
-                    const R tte = t * te;
-                    C += tte;
+                    C += tw[2] * e;
                     if constexpr (sizeof(R) == 8)
-                        D3 += t * tte;
-                    Av0 += fast_exp(xv0);
-                    Av1 += fast_exp(xv1);
-                    At0 += fast_exp(xt0);
-                    At1 += fast_exp(xt1);
+                        D3 += tw[3] * e;
+                    Av0 += tw[0] * exp2r(yv0);
+                    Av1 += tw[0] * exp2r(yv1);
+                    At0 += tw[4] * exp2r(yt0);
+                    At1 += tw[5] * exp2r(yt1);
                 }
             }
         }
@@ -127,47 +181,20 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
     if constexpr (RNG == 0) {
         // Philox: counter (j >> 1, lo32 p, hi32 p, 0); words (0,1) even step, (2,3) odd step.
         const uint32_t k0 = (uint32_t)L.seed, k1 = (uint32_t)(L.seed >> 32);
-        const uint32_t plo = (uint32_t)p, phi = (uint32_t)(p >> 32);
-        R *ck = reinterpret_cast<R *>(L.ckpt);
-        const uint64_t np = L.n_paths, row = p - L.first_path;
+        // Paths below 2^32 have a zero high counter word: the first round's
+        // second product is then zero and the compiler keeps it scalar.
+        const uint32_t plo = (uint32_t)p, phi = L.wide_paths ? (uint32_t)(p >> 32) : 0u;
         uint32_t j = 0;
         for (; j + 1 < N; j += 2) {
-            if (ck != nullptr && j % L.ckpt_every == 0 && active) {
-                const uint64_t c = j / L.ckpt_every;
-                ck[(2 * c) * np + row] = x;
-                ck[(2 * c + 1) * np + row] = v;
-            }
-            const U4 w = philox4x32_10(U4{j >> 1, plo, phi, 0u}, k0, k1);
-            R za, zb;
-            if constexpr (sizeof(R) == 4)
-                box_muller(uniform_f32(w.x), uniform_f32(w.y), za, zb);
-            else
-                box_muller(uniform_f64(w.x), uniform_f64(w.y), za, zb);
-            step(j, za, zb);
-            if constexpr (sizeof(R) == 4)
-                box_muller(uniform_f32(w.z), uniform_f32(w.w), za, zb);
-            else
-                box_muller(uniform_f64(w.z), uniform_f64(w.w), za, zb);
-            step(j + 1, za, zb);
+            R za0, zb0, za1, zb1;
+            philox_normals<R>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
+            step(j, za0, zb0);
+            step(j + 1, za1, zb1);
         }
         if (j < N) {
-            if (ck != nullptr && j % L.ckpt_every == 0 && active) {
-                const uint64_t c = j / L.ckpt_every;
-                ck[(2 * c) * np + row] = x;
-                ck[(2 * c + 1) * np + row] = v;
-            }
-            const U4 w = philox4x32_10(U4{j >> 1, plo, phi, 0u}, k0, k1);
-            R za, zb;
-            if constexpr (sizeof(R) == 4)
-                box_muller(uniform_f32(w.x), uniform_f32(w.y), za, zb);
-            else
-                box_muller(uniform_f64(w.x), uniform_f64(w.y), za, zb);
-            step(j, za, zb);
-        }
-        if (ck != nullptr && active) {
-            const uint64_t c = ckpt_count(N, L.ckpt_every);
-            ck[(2 * c) * np + row] = x;
-            ck[(2 * c + 1) * np + row] = A;
+            R za0, zb0, za1, zb1;
+            philox_normals<R>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
+            step(j, za0, zb0);
         }
     } else {
         // Sobol point i of replicate `rep`, Brownian bridge walked in time order
@@ -183,10 +210,30 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         while (nbits < 30 && (M - 1) >> nbits)
             ++nbits;
         const uint32_t *shift = L.sobol_shift + (uint64_t)rep * 2u * N;
+        // When every wave covers 64 consecutive points starting at a multiple of
+        // 64, Gray-code bits 6 and up are the same in all its lanes: their XOR of
+        // direction numbers is wave-uniform (scalar), and each lane only combines
+        // six direction numbers under its fixed masks.
+        const bool aligned = (M % 64 == 0) && ((lo - rep_lo) % 64 == 0);
+        const uint32_t g_hi = __builtin_amdgcn_readfirstlane(g) & ~63u;
+        uint32_t m[6];
+#pragma unroll
+        for (int b = 0; b < 6; ++b)
+            m[b] = 0u - ((g >> b) & 1u);
+        auto coord = [&](uint32_t d) -> uint32_t {
+            const uint32_t *v = L.sobol_dirs + 32u * d;
+            if (aligned) {
+                uint32_t u = shift[d];
+                for (uint32_t bits = g_hi; bits; bits &= bits - 1)
+                    u ^= v[__builtin_ctz(bits)];
+                return u ^ sobol_low(v, m);
+            }
+            return sobol_coord(L.sobol_dirs, d, g, nbits, shift[d]);
+        };
         auto node_normals = [&](int k, R &wa, R &wb) {
             const uint32_t d = 2u * (uint32_t)k;
-            wa = sobol_normal<R>(sobol_coord(L.sobol_dirs, d, g, nbits, shift[d]));
-            wb = sobol_normal<R>(sobol_coord(L.sobol_dirs, d + 1, g, nbits, shift[d + 1]));
+            wa = sobol_normal<R>(coord(d));
+            wb = sobol_normal<R>(coord(d + 1));
         };
         R ca = 0, cbm = 0; // B_j of the two motions
         {
@@ -224,29 +271,30 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
     }
 
     // ---- payoffs and Greek samples, in FP64 ----
-    double y[N_EST];
+    double est[N_EST];
     const Payoff pay{L.opt_type, L.K, 1.0 / (double)L.n_fix};
     const double S0 = L.S0, D = exp(-L.r * L.T);
-    const double eT = exp((double)x);
+    const double x = (double)y * LN2 + L.r * L.T;
+    const double eT = exp(x);
     const double ST = S0 * eT;
     const double rel = ASIAN ? (double)A * pay.inv_nfix : eT; // Sbar / S0 (or S_T / S0)
     const double X = S0 * rel;
     const double sgn = pay.call() ? 1.0 : -1.0;
     const bool itm = sgn * (X - L.K) > 0.0;
-    y[EST_PRICE] = pay(D, X);
-    y[EST_PW_DELTA] = itm ? sgn * D * rel : 0.0;
+    est[EST_PRICE] = pay(D, X);
+    est[EST_PW_DELTA] = itm ? sgn * D * rel : 0.0;
     if (ASIAN)
-        y[EST_PW_RHO] = itm ? D * (sgn * S0 * (double)B * pay.inv_nfix - L.T * sgn * (X - L.K)) : 0.0;
+        est[EST_PW_RHO] = itm ? D * (sgn * S0 * (double)B * pay.inv_nfix - L.T * sgn * (X - L.K)) : 0.0;
     else
-        y[EST_PW_RHO] = itm ? sgn * D * L.K * L.T : 0.0;
+        est[EST_PW_RHO] = itm ? sgn * D * L.K * L.T : 0.0;
 
     double sc[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // S0+, S0-, v0+, v0-, r+, r-, T+, T-
     if constexpr (BUMPS) {
         const double hS = L.hS, hr = L.hr;
         sc[0] = pay(D, (S0 + hS) * rel);
         sc[1] = pay(D, (S0 - hS) * rel);
-        const double Xv0 = S0 * (ASIAN ? (double)Av0 * pay.inv_nfix : exp((double)xv0));
-        const double Xv1 = S0 * (ASIAN ? (double)Av1 * pay.inv_nfix : exp((double)xv1));
+        const double Xv0 = S0 * (ASIAN ? (double)Av0 * pay.inv_nfix : exp((double)yv0 * LN2 + L.r * L.T));
+        const double Xv1 = S0 * (ASIAN ? (double)Av1 * pay.inv_nfix : exp((double)yv1 * LN2 + L.r * L.T));
         sc[2] = pay(D, Xv0);
         sc[3] = pay(D, Xv1);
         const double Dup = exp(-(L.r + hr) * L.T), Ddn = exp(-(L.r - hr) * L.T);
@@ -264,37 +312,37 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         sc[4] = pay(Dup, Xu);
         sc[5] = pay(Ddn, Xd);
         const double Tu = L.T + L.hT, Td = L.T - L.hT;
-        const double Xt0 = S0 * (ASIAN ? (double)At0 * pay.inv_nfix : exp((double)xt0));
-        const double Xt1 = S0 * (ASIAN ? (double)At1 * pay.inv_nfix : exp((double)xt1));
+        const double Xt0 = S0 * (ASIAN ? (double)At0 * pay.inv_nfix : exp((double)yt0 * LN2 + L.r * Tu));
+        const double Xt1 = S0 * (ASIAN ? (double)At1 * pay.inv_nfix : exp((double)yt1 * LN2 + L.r * Td));
         sc[6] = pay(exp(-L.r * Tu), Xt0);
         sc[7] = pay(exp(-L.r * Td), Xt1);
-        y[EST_DELTA] = (sc[0] - sc[1]) / (2.0 * hS);
-        y[EST_GAMMA] = (sc[0] - 2.0 * y[EST_PRICE] + sc[1]) / (hS * hS);
-        y[EST_VEGA] = (sc[2] - sc[3]) / (2.0 * L.hv);
-        y[EST_RHO] = (sc[4] - sc[5]) / (2.0 * hr);
-        y[EST_THETA] = -(sc[6] - sc[7]) / (2.0 * L.hT);
+        est[EST_DELTA] = (sc[0] - sc[1]) / (2.0 * hS);
+        est[EST_GAMMA] = (sc[0] - 2.0 * est[EST_PRICE] + sc[1]) / (hS * hS);
+        est[EST_VEGA] = (sc[2] - sc[3]) / (2.0 * L.hv);
+        est[EST_RHO] = (sc[4] - sc[5]) / (2.0 * hr);
+        est[EST_THETA] = -(sc[6] - sc[7]) / (2.0 * L.hT);
     } else {
 #pragma unroll
         for (int e = EST_DELTA; e < N_EST; ++e)
-            y[e] = 0.0;
+            est[e] = 0.0;
     }
 
     if (L.pay_out != nullptr && active)
-        L.pay_out[p - L.first_path] = y[EST_PRICE];
+        L.pay_out[p - L.first_path] = est[EST_PRICE];
 
     if (L.dump != nullptr && active) {
         double *rec = L.dump + (p - L.first_path) * DUMP_WIDTH;
         rec[0] = ST;
-        rec[1] = (double)v;
+        rec[1] = (double)w / L.base.dt;
         rec[2] = X;
-        rec[3] = y[EST_PRICE];
-        rec[4] = y[EST_PW_DELTA];
-        rec[5] = y[EST_PW_RHO];
+        rec[3] = est[EST_PRICE];
+        rec[4] = est[EST_PW_DELTA];
+        rec[5] = est[EST_PW_RHO];
         const double nan = __builtin_nan("");
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             rec[6 + k] = BUMPS ? sc[k] : nan;
-        rec[14] = (double)x;
+        rec[14] = x;
         rec[15] = 0.0;
     }
 
@@ -302,7 +350,7 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int e = 0; e < N_EST; ++e) {
-        const double ye = active ? y[e] : 0.0;
+        const double ye = active ? est[e] : 0.0;
         const double s1 = wave_sum(ye);
         const double s2 = wave_sum(ye * ye);
         if (lane == 0) {
@@ -397,17 +445,47 @@ __global__ __launch_bounds__(BLOCK) void bump_combine_kernel(const double *__res
     }
 }
 
-// Fixed-order sum of `rows` records of width w (w <= BLOCK): thread k sums column k.
+// Fixed-order sum of `rows` records of width w (w <= BLOCK): the block's
+// floor(BLOCK / w) groups of w threads take rows g, g + groups, ... (thread k
+// of a group owns column k); the group sums are then added in group order.
 __global__ __launch_bounds__(BLOCK) void reduce_rows_kernel(const double *__restrict__ partials,
                                                             uint32_t rows, uint32_t w,
                                                             double *__restrict__ out)
 {
-    if (threadIdx.x >= w)
-        return;
+    __shared__ double red[BLOCK];
+    const uint32_t groups = BLOCK / w;
+    const uint32_t grp = threadIdx.x / w, col = threadIdx.x % w;
     double t = 0.0;
-    for (uint32_t r = 0; r < rows; ++r)
-        t += partials[(uint64_t)r * w + threadIdx.x];
-    out[threadIdx.x] = t;
+    if (grp < groups)
+        for (uint32_t r = grp; r < rows; r += groups)
+            t += partials[(uint64_t)r * w + col];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x < w) {
+        double s = 0.0;
+        for (uint32_t g = 0; g < groups; ++g)
+            s += red[g * w + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+template <class R>
+__global__ void step_weights_kernel(uint32_t n, double r, double dt, double dt_up, double dt_dn,
+                                    R *out)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n)
+        return;
+    const double t = (double)(j + 1) * dt, g = exp(r * t);
+    R *o = out + (uint64_t)STEP_WEIGHTS * j;
+    o[0] = (R)g;
+    o[1] = (R)(t * g);
+    o[2] = (R)(t * t * g);
+    o[3] = (R)(t * t * t * g);
+    o[4] = (R)exp(r * (double)(j + 1) * dt_up);
+    o[5] = (R)exp(r * (double)(j + 1) * dt_dn);
+    o[6] = (R)0;
+    o[7] = (R)0;
 }
 
 // Digital shifts of the Sobol replicates: shift[r][d] = top 30 bits of word 0
@@ -456,6 +534,19 @@ template <class R> hipError_t launch_r(const PriceLaunch &L, hipStream_t s)
 }
 
 } // namespace
+
+hipError_t launch_step_weights(const PriceLaunch &L, void *out, hipStream_t stream)
+{
+    const uint32_t n = L.n_steps;
+    const double du = L.bumps ? L.tup.dt : L.base.dt, dd = L.bumps ? L.tdn.dt : L.base.dt;
+    if (L.precision == 0)
+        hipLaunchKernelGGL(step_weights_kernel<double>, dim3((n + 255) / 256), dim3(256), 0, stream,
+                           n, L.r, L.base.dt, du, dd, (double *)out);
+    else
+        hipLaunchKernelGGL(step_weights_kernel<float>, dim3((n + 255) / 256), dim3(256), 0, stream,
+                           n, L.r, L.base.dt, du, dd, (float *)out);
+    return hipGetLastError();
+}
 
 hipError_t launch_sobol_shifts(uint64_t seed, uint32_t dims, uint32_t reps, uint32_t *out,
                                hipStream_t stream)

@@ -21,7 +21,7 @@ struct heston_ctx {
     uint64_t budget = 0; // 0 = unlimited
     uint64_t in_use = 0; // bytes held by the buffers below
     DevBuf partials, rep_sums, fix_bits, sobol_dirs, sobol_shift, bridge_start, bridge_ops;
-    DevBuf pay, bump_partials, bump_sums;
+    DevBuf pay, bump_partials, bump_sums, step_w;
     DevBuf batch_opts, batch_items, batch_partials, batch_sums, batch_counter, batch_scratch;
     double *host_sums = nullptr; // pinned
     size_t host_sums_bytes = 0;

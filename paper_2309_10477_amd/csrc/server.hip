@@ -213,7 +213,7 @@ struct Req {
     uint32_t cap_items = 0;
     uint32_t scheduled = 0;   // items launched so far (items [0, scheduled))
     uint32_t folded = 0;      // items folded (from the last completed launch)
-    uint32_t target = 8;      // items the engine currently aims for
+    uint32_t target = 16;     // items the engine currently aims for
     uint32_t inflight = 0;    // launches holding items of this request
     bool done = false;
     unsigned char *mem = nullptr; // state then item records, in the pool
@@ -584,7 +584,7 @@ heston_status heston_server_default_config(heston_server_config *c)
     c->max_active = 4096;
     c->max_steps = 2048;
     c->hbm_budget_bytes = 8ull << 30;
-    c->launch_path_steps = 1ull << 31;
+    c->launch_path_steps = 1ull << 29;
     return HESTON_OK;
 }
 
