@@ -30,12 +30,13 @@ METRIC = "path-steps/s incl. Greeks, adjoint vs bump-revalue; p50/p99 request la
 
 # Vector-ALU operations per path-step of the dominant kernel (FP32, Philox,
 # Asian with a fixing every step, fused bumps = 5 path states, full
-# truncation), counted from the method's arithmetic, one per elementary
-# operation (FMA, transcendental, 32x32->64 multiply, XOR, compare/select and
-# conversion each count 1): Philox half block 30, two uniforms 6, Box-Muller 7,
-# correlation and shared Milstein terms 7, five state updates 5 x 10, fixing
-# sums 10 + 4 x 3.  Derivation in the design doc.
-OPS_PER_PATH_STEP = 122.0
+# truncation), counted from the method's arithmetic as this kernel formulates
+# it, one per elementary lane operation (FMA, transcendental, 32x32->64
+# multiply, two-input XOR, shift, compare/select each count 1): Philox half
+# block 30, two uniforms 6, Box-Muller 7, correlation and the per-grid
+# Milstein coefficients 10, five state updates 5 x 7, fixing exponentials and
+# weighted sums 5 + 7.  Derivation in the design doc.
+OPS_PER_PATH_STEP = 100.0
 # Published FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-operations/s
 # (256 CUs x 128 lanes/clk x 2.4 GHz); every counted operation is priced as one
 # such lane-operation.

@@ -285,6 +285,19 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
         HIP_TRY(hipMemcpyAsync(c->sobol_dirs.ptr, o.sobol_directions, (size_t)dims * 32 * 4,
                                hipMemcpyHostToDevice, c->stream));
         HIP_TRY(launch_sobol_shifts(q.seed, dims, R, (uint32_t *)c->sobol_shift.ptr, c->stream));
+        // Blocks of 64 consecutive points share their Gray-code bits >= 6; when the
+        // launch's waves are block-aligned, the XOR of those bits' direction numbers
+        // is tabulated once per block and dimension (a kernel that would otherwise
+        // walk the set bits with one scalar load each, per dimension and wave).
+        L.sobol_hi = nullptr;
+        const uint64_t n_blk = (M + 63) / 64, hi_bytes = n_blk * dims * 4;
+        if (M % 64 == 0 && (first % M) % 64 == 0 && hi_bytes <= SOBOL_HI_MAX_BYTES) {
+            if ((st = reserve(c, c->sobol_hi, hi_bytes)) != HESTON_OK)
+                return st;
+            HIP_TRY(launch_sobol_hi((const uint32_t *)c->sobol_dirs.ptr, dims, (uint32_t)n_blk,
+                                    (uint32_t *)c->sobol_hi.ptr, c->stream));
+            L.sobol_hi = (const uint32_t *)c->sobol_hi.ptr;
+        }
         HIP_TRY(hipMemcpyAsync(c->bridge_start.ptr, bp.start.data(), (q.n_steps + 1) * 4,
                                hipMemcpyHostToDevice, c->stream));
         if (!bp.ops.empty())
@@ -547,7 +560,7 @@ heston_status heston_ctx_destroy(heston_ctx *c)
         return fail(HESTON_INVALID_ARGUMENT, "ctx is NULL");
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift,
+    for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift, &c->sobol_hi,
                       &c->bridge_start, &c->bridge_ops, &c->pay, &c->bump_partials,
                       &c->bump_sums, &c->step_w, &c->batch_opts, &c->batch_items, &c->batch_partials,
                       &c->batch_sums, &c->batch_counter, &c->batch_scratch})

@@ -12,7 +12,10 @@ namespace heston {
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round
 // multiplies counter words 0 and 2 by fixed 32-bit constants (full 64-bit
 // products), mixes the high halves with words 1, 3 and the key, and the key
-// then advances by the two Weyl constants.
+// then advances by the two Weyl constants.  From the third round on every
+// word is per-lane, and each three-way XOR is one v_bitop3_b32 (truth table
+// 0x96); the first two rounds are left to the compiler, which keeps their
+// wave-uniform parts on the scalar unit.
 struct U4 {
     uint32_t x, y, z, w;
 };
@@ -27,7 +30,11 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
         const uint64_t p1 = (uint64_t)M1 * c.z;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        if (i >= 2)
+            c = U4{(uint32_t)__builtin_amdgcn_bitop3_b32(hi1, c.y, k0, 0x96), lo1,
+                   (uint32_t)__builtin_amdgcn_bitop3_b32(hi0, c.w, k1, 0x96), lo0};
+        else
+            c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
         k0 += W0;
         k1 += W1;
     }
@@ -35,10 +42,12 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 }
 
 // Uniform in (0,1) from the top 23 bits of a word: (m + 1/2) 2^-23, exact in
-// binary32 and binary64.
+// binary32 and binary64.  Single precision builds 1 + m 2^-23 by placing m
+// under the exponent of 1.0 and subtracts 1 - 2^-24; the difference is
+// representable, so it is exact (no integer-to-float conversion).
 __device__ __forceinline__ float uniform_f32(uint32_t w)
 {
-    return __uint2float_rn(w >> 9) * 0x1p-23f + 0x1p-24f;
+    return __uint_as_float(0x3F800000u | (w >> 9)) - 0x1.fffffep-1f;
 }
 __device__ __forceinline__ double uniform_f64(uint32_t w)
 {

@@ -23,6 +23,9 @@ constexpr int N_ACC = 2 * N_EST;   // doubles per partial record
 constexpr int DUMP_WIDTH = 16;
 constexpr int BLOCK = 256;         // threads per block of the path kernels
 constexpr int MAX_BRIDGE_DEPTH = 24;
+// Largest per-block Sobol table (ceil(M/64) x 2N words) built for a launch;
+// above it the kernel combines the high direction numbers itself.
+constexpr uint64_t SOBOL_HI_MAX_BYTES = 256ull << 20;
 // Fixing weights per step j (fixing time t = (j+1) dt): e^{rt}, t e^{rt},
 // t^2 e^{rt}, t^3 e^{rt} on the base grid, e^{rt} on the T + hT and T - hT grids.
 constexpr int STEP_WEIGHTS = 8;
@@ -64,6 +67,8 @@ struct PriceLaunch {
     // quasi-random
     const uint32_t *sobol_dirs;     // device [2N][32]
     const uint32_t *sobol_shift;    // device [R][2N]
+    const uint32_t *sobol_hi;       // device [ceil(M/64)][2N] or null: per 64-point block,
+                                    // XOR of the direction numbers of Gray-code bits >= 6
     const int32_t *bridge_start;    // device [N+1]: ops of step j are [start[j], start[j+1])
     const BridgeOp *bridge_ops;     // device [N-1]
     double bridge_root_scale;       // sqrt(N)
@@ -176,6 +181,8 @@ hipError_t launch_reduce(const PriceLaunch &L, double *rep_sums, hipStream_t str
 hipError_t launch_step_weights(const PriceLaunch &L, void *out, hipStream_t stream);
 
 // Writes the [reps][dims] digital shifts of the Sobol replicates of `seed`.
+hipError_t launch_sobol_hi(const uint32_t *dirs, uint32_t dims, uint32_t n_blk, uint32_t *out,
+                           hipStream_t stream);
 hipError_t launch_sobol_shifts(uint64_t seed, uint32_t dims, uint32_t reps, uint32_t *out,
                                hipStream_t stream);
 

@@ -81,12 +81,13 @@ template <class R> struct Grid {
     R qdt2;  // sigma^2 dt^2 / 4
     R sdt;   // sigma dt
     R dt;
+    R kdt_h; // kappa dt / 2
 };
 
 template <class R> __device__ __forceinline__ Grid<R> grid(const StepCoef &c, double sigma)
 {
     return Grid<R>{(R)c.kappa_dt, (R)(c.kappa_theta_dt * c.dt), (R)(c.quarter_sigma2_dt * c.dt),
-                   (R)(sigma * c.dt), (R)c.dt};
+                   (R)(sigma * c.dt), (R)c.dt, (R)(0.5 * c.kappa_dt)};
 }
 
 // max(w, 0) as one v_med3 (no NaN canonicalisation of the loop-carried w).
@@ -99,9 +100,24 @@ __device__ __forceinline__ double exp2r(double y) { return exp2(y); }
 // sigma^2 dt^2 (Z2^2 - 1) / 4, s_g = sigma dt Z2.  y leaves out the
 // deterministic drift r t / ln 2, which is added back where S is needed: at
 // the end of the path, and at a fixing date through the weight e^{r t_j}.
+// Under full truncation the clamp is taken as w + |w| = 2 max(w, 0), one
+// plain add (exact), and the factor 2 is carried by the constants: the caller
+// passes z1l and s_g divided by sqrt 2 (FT_SCALE).
+template <class R, bool FT> constexpr R FT_SCALE = FT ? (R)0.70710678118654752440 : R(1);
+
 template <class R, bool FT>
 __device__ __forceinline__ void scaled_step(R &y, R &w, const Grid<R> &g, R z1l, R a_g, R s_g)
 {
+    if constexpr (FT) {
+        constexpr R QUARTER_LOG2E = (R)(0.25 * LOG2E);
+        const R vp2 = w + fabs(w);
+        const R s = fast_sqrt(vp2); // sqrt 2 x sqrt(V+ dt)
+        y = y - QUARTER_LOG2E * vp2;
+        y = y + s * z1l;
+        w = w + (a_g - g.kdt_h * vp2);
+        w = w + s * s_g;
+        return;
+    }
     constexpr R HALF_LOG2E = (R)(0.5 * LOG2E);
     const R vp = clamp0(w);
     const R s = fast_sqrt(vp);
@@ -146,16 +162,17 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
 
     // One step given the independent normals (za, zb) of step j.
     auto step = [&](uint32_t j, R za, R zb) {
-        const R z1l = za * log2e;
+        constexpr R FS = FT_SCALE<R, FT>;
+        const R z1l = za * (log2e * FS);
         const R z2 = rho * za + rho_bar * zb;
         const R z2m1 = z2 * z2 - R(1);
-        const R ab = gb.ktdt2 + gb.qdt2 * z2m1, sb = gb.sdt * z2;
+        const R ab = gb.ktdt2 + gb.qdt2 * z2m1, sb = (gb.sdt * FS) * z2;
         scaled_step<R, FT>(y, w, gb, z1l, ab, sb);
         if constexpr (BUMPS) {
             scaled_step<R, FT>(yv0, wv0, gb, z1l, ab, sb);
             scaled_step<R, FT>(yv1, wv1, gb, z1l, ab, sb);
-            scaled_step<R, FT>(yt0, wt0, gu, z1l, gu.ktdt2 + gu.qdt2 * z2m1, gu.sdt * z2);
-            scaled_step<R, FT>(yt1, wt1, gd, z1l, gd.ktdt2 + gd.qdt2 * z2m1, gd.sdt * z2);
+            scaled_step<R, FT>(yt0, wt0, gu, z1l, gu.ktdt2 + gu.qdt2 * z2m1, (gu.sdt * FS) * z2);
+            scaled_step<R, FT>(yt1, wt1, gd, z1l, gd.ktdt2 + gd.qdt2 * z2m1, (gd.sdt * FS) * z2);
         }
         if constexpr (ASIAN) {
             if (is_fixing(L.fix_bits, j + 1)) {
@@ -220,12 +237,19 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
 #pragma unroll
         for (int b = 0; b < 6; ++b)
             m[b] = 0u - ((g >> b) & 1u);
+        const uint32_t *hi_row =
+            L.sobol_hi ? L.sobol_hi + (uint64_t)(__builtin_amdgcn_readfirstlane((uint32_t)i) >> 6) * 2u * N
+                       : nullptr;
         auto coord = [&](uint32_t d) -> uint32_t {
             const uint32_t *v = L.sobol_dirs + 32u * d;
             if (aligned) {
                 uint32_t u = shift[d];
-                for (uint32_t bits = g_hi; bits; bits &= bits - 1)
-                    u ^= v[__builtin_ctz(bits)];
+                if (hi_row != nullptr) {
+                    u ^= hi_row[d];
+                } else {
+                    for (uint32_t bits = g_hi; bits; bits &= bits - 1)
+                        u ^= v[__builtin_ctz(bits)];
+                }
                 return u ^ sobol_low(v, m);
             }
             return sobol_coord(L.sobol_dirs, d, g, nbits, shift[d]);
@@ -488,6 +512,23 @@ __global__ void step_weights_kernel(uint32_t n, double r, double dt, double dt_u
     o[7] = (R)0;
 }
 
+// Per 64-point block b of a replicate and dimension d: the XOR of the
+// direction numbers v[d][k] over the set bits k >= 6 of the Gray code of
+// 64 b, which every point of the block shares (Gray code g(i) = i ^ (i >> 1)).
+__global__ void sobol_hi_kernel(const uint32_t *dirs, uint32_t dims, uint32_t n_blk, uint32_t *out)
+{
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (uint64_t)dims * n_blk)
+        return;
+    const uint32_t b = (uint32_t)(idx / dims), d = (uint32_t)(idx - (uint64_t)b * dims);
+    const uint32_t i = b << 6;
+    const uint32_t *v = dirs + 32u * d;
+    uint32_t x = 0;
+    for (uint32_t bits = (i ^ (i >> 1)) & ~63u; bits; bits &= bits - 1)
+        x ^= v[__builtin_ctz(bits)];
+    out[idx] = x;
+}
+
 // Digital shifts of the Sobol replicates: shift[r][d] = top 30 bits of word 0
 // of Philox4x32-10(counter (d, r, 0, 1), key = seed).
 __global__ void sobol_shift_kernel(uint64_t seed, uint32_t dims, uint32_t reps, uint32_t *out)
@@ -545,6 +586,15 @@ hipError_t launch_step_weights(const PriceLaunch &L, void *out, hipStream_t stre
     else
         hipLaunchKernelGGL(step_weights_kernel<float>, dim3((n + 255) / 256), dim3(256), 0, stream,
                            n, L.r, L.base.dt, du, dd, (float *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sobol_hi(const uint32_t *dirs, uint32_t dims, uint32_t n_blk, uint32_t *out,
+                           hipStream_t stream)
+{
+    const uint64_t n = (uint64_t)dims * n_blk;
+    hipLaunchKernelGGL(sobol_hi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       dirs, dims, n_blk, out);
     return hipGetLastError();
 }
 
