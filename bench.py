@@ -8,8 +8,10 @@ all estimators reduced across paths and copied to the host.  Inputs are
 parameters only (nothing to stage); the timed region covers the library call.
 
 Prints ONE JSON line (rank 0).  Also reported: the roofline of the path kernel
-(operation-count model), the Sobol + Brownian-bridge variant of the
-same step, and the CPU oracle timed on a bounded sample of the same workload.
+(an operation count per path-step against the FP32 vector peak), the Sobol +
+Brownian-bridge variant of the same step, the adjoint against plain
+bump-and-revalue, the 4096-option batch, the serving loop's latency, and the
+CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -35,7 +37,7 @@ METRIC = "path-steps/s incl. Greeks, adjoint vs bump-revalue; p50/p99 request la
 # multiply, two-input XOR, shift, compare/select each count 1): Philox half
 # block 30, two uniforms 6, Box-Muller 7, correlation and the per-grid
 # Milstein coefficients 10, five state updates 5 x 7, fixing exponentials and
-# weighted sums 5 + 7.  Derivation in the design doc.
+# weighted sums 5 + 7.
 OPS_PER_PATH_STEP = 100.0
 # Published FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-operations/s
 # (256 CUs x 128 lanes/clk x 2.4 GHz); every counted operation is priced as one
@@ -46,7 +48,7 @@ ALU_PEAK_OPS = 256 * 128 * 2.4e9
 # a 256 MiB device copy reads under the same counters); see
 # profiles/price_kernel_asian_2p20x252_fp32_bumps_hbm_counters.md.  Set to None
 # whenever the kernel changes until the counters are taken again.
-TRAFFIC_BYTES_PER_LAUNCH = None
+TRAFFIC_BYTES_PER_LAUNCH = 835_886
 
 
 def parse():
@@ -217,8 +219,9 @@ def serving(ctx, hm, torch, n_measured=1000, n_warm=100):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by path index, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(paths would shard across GPUs by path index, with one all-reduce of the "
+              "FP64 partial sums)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2309_10477_amd as hm

@@ -291,12 +291,20 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
         // walk the set bits with one scalar load each, per dimension and wave).
         L.sobol_hi = nullptr;
         const uint64_t n_blk = (M + 63) / 64, hi_bytes = n_blk * dims * 4;
-        if (M % 64 == 0 && (first % M) % 64 == 0 && hi_bytes <= SOBOL_HI_MAX_BYTES) {
-            if ((st = reserve(c, c->sobol_hi, hi_bytes)) != HESTON_OK)
+        // The table is an accelerator only: without room for it under the
+        // context budget (or device memory) the kernel takes the slower path.
+        const bool fits = !c->budget || c->in_use - c->sobol_hi.bytes + hi_bytes <= c->budget;
+        if (M % 64 == 0 && (first % M) % 64 == 0 && hi_bytes <= SOBOL_HI_MAX_BYTES && fits) {
+            st = reserve(c, c->sobol_hi, hi_bytes);
+            if (st == HESTON_OK) {
+                HIP_TRY(launch_sobol_hi((const uint32_t *)c->sobol_dirs.ptr, dims, (uint32_t)n_blk,
+                                        (uint32_t *)c->sobol_hi.ptr, c->stream));
+                L.sobol_hi = (const uint32_t *)c->sobol_hi.ptr;
+            } else if (st == HESTON_OUT_OF_MEMORY || st == HESTON_OVER_BUDGET) {
+                g_last_error.clear();
+            } else {
                 return st;
-            HIP_TRY(launch_sobol_hi((const uint32_t *)c->sobol_dirs.ptr, dims, (uint32_t)n_blk,
-                                    (uint32_t *)c->sobol_hi.ptr, c->stream));
-            L.sobol_hi = (const uint32_t *)c->sobol_hi.ptr;
+            }
         }
         HIP_TRY(hipMemcpyAsync(c->bridge_start.ptr, bp.start.data(), (q.n_steps + 1) * 4,
                                hipMemcpyHostToDevice, c->stream));

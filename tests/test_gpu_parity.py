@@ -178,10 +178,25 @@ def test_sobol_bridge_full_size_sampled(hm, ctx):
     R, M, N, seed = 16, 1 << 16, 252, 42
     n = R * M
     opts = hm.Options(precision=hm.FP32, rng=hm.SOBOL_BRIDGE, qmc_replicates=R)
-    for first in (0, 5 * M - 300, n - 500):
+    # first = 0 and 3M + 64 * 1001 are 64-point aligned (per-block high-part
+    # table; block 1001 has five Gray-code bits >= 6 set), the others are not
+    for first in (0, 3 * M + 64 * 1001, 5 * M - 300, n - 500):
         d = dump(hm, ctx, PB, hm.ASIAN_CALL, n, N, seed, first, 500, opts)
         za, zb = sobol.normals(N, first, 500, R, M, seed)
         check_records(d, PB, oracle.ASIAN_CALL, N, seed, first, 500, 1, 0, None, True, za, zb)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sobol_aligned_table_equals_generic_points(hm, ctx, prec):
+    """Launches whose waves start on 64-point blocks take the high Gray-code
+    part of each point from a per-block table; a launch shifted by one path
+    combines every direction number itself.  Both give the same records."""
+    R, M, N, seed = 2, 1 << 14, 8, 7
+    n = R * M
+    opts = hm.Options(precision=prec, rng=hm.SOBOL_BRIDGE, qmc_replicates=R)
+    a = dump(hm, ctx, PB, hm.ASIAN_PUT, n, N, seed, 0, n, opts)
+    b = dump(hm, ctx, PB, hm.ASIAN_PUT, n, N, seed, 1, n - 1, opts)
+    np.testing.assert_array_equal(a[1:], b)
 
 
 def test_path_index_above_2_32_and_wide_seed(hm, ctx):
