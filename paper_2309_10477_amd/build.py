@@ -1,5 +1,13 @@
 """Builds libheston.so for gfx950 with hipcc, in-tree.
 
+Each source is compiled to its own object (in parallel, under
+paper_2309_10477_amd/_build/), then the objects are linked into the shared
+library.  Per-file flags carry code-generation choices measured on the
+hardware: the pricing kernels' file is scheduled for instruction-level
+parallelism (gfx950 issues two VALU instructions per quad-cycle only from two
+different waves, and a denser interleave of independent chains keeps more
+waves ready: 3% faster on the fused path kernel, with 70 instead of 61 VGPRs).
+
 Usage: python -m paper_2309_10477_amd.build   (or call build()).
 """
 from __future__ import annotations
@@ -7,29 +15,50 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("api.hip", "price_kernel.hip",
-                                               "adjoint_kernel.hip", "batch_kernel.hip",
-                                               "batch_api.hip", "server.hip")]
+SOURCES = ("api.hip", "price_kernel.hip", "adjoint_kernel.hip", "batch_kernel.hip",
+           "batch_api.hip", "server.hip")
+SRC = [os.path.join(HERE, "csrc", f) for f in SOURCES]
 HDRS = [os.path.join(HERE, "csrc", f) for f in ("internal.hpp", "device_math.hpp",
-                                                "path_step.hpp")] + \
+                                                "path_step.hpp", "runtime.hpp",
+                                                "batch_plan.hpp")] + \
     [os.path.join(os.path.dirname(HERE), "include", "heston.h")]
 LIB = os.path.join(HERE, "libheston.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("HESTON_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
+PER_FILE = {
+    "price_kernel.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+}
+
+
+def _compile(hipcc: str, src: str, verbose: bool) -> str:
+    name = os.path.basename(src)
+    obj = os.path.join(OBJ_DIR, name + ".o")
+    cmd = [hipcc, *FLAGS, *PER_FILE.get(name, []), "-c", "-o", obj + ".tmp", src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(obj + ".tmp", obj)
+    return obj
 
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    workers = max(1, min(len(SRC), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(workers) as ex:
+        objs = list(ex.map(lambda s: _compile(hipcc, s, verbose), SRC))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-o", tmp, *SRC]
+    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
