@@ -284,27 +284,60 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
             return st;
         HIP_TRY(hipMemcpyAsync(c->sobol_dirs.ptr, o.sobol_directions, (size_t)dims * 32 * 4,
                                hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(launch_sobol_shifts(q.seed, dims, R, (uint32_t *)c->sobol_shift.ptr, c->stream));
         // Blocks of 64 consecutive points share their Gray-code bits >= 6; when the
         // launch's waves are block-aligned, the XOR of those bits' direction numbers
-        // is tabulated once per block and dimension (a kernel that would otherwise
-        // walk the set bits with one scalar load each, per dimension and wave).
+        // is tabulated once per block and dimension, and the shifts, that table and
+        // the six low direction numbers of each node are laid out in the order the
+        // bridge walk consumes its nodes, so the kernel addresses them by walk
+        // position instead of through each op's node index.  The tables are an
+        // accelerator only: without room for them under the context budget (or in
+        // device memory) the kernel combines the direction numbers itself.
         L.sobol_hi = nullptr;
+        L.sobol_dir12 = nullptr;
+        const uint32_t N = q.n_steps;
         const uint64_t n_blk = (M + 63) / 64, hi_bytes = n_blk * dims * 4;
-        // The table is an accelerator only: without room for it under the
-        // context budget (or device memory) the kernel takes the slower path.
-        const bool fits = !c->budget || c->in_use - c->sobol_hi.bytes + hi_bytes <= c->budget;
-        if (M % 64 == 0 && (first % M) % 64 == 0 && hi_bytes <= SOBOL_HI_MAX_BYTES && fits) {
-            st = reserve(c, c->sobol_hi, hi_bytes);
-            if (st == HESTON_OK) {
-                HIP_TRY(launch_sobol_hi((const uint32_t *)c->sobol_dirs.ptr, dims, (uint32_t)n_blk,
-                                        (uint32_t *)c->sobol_hi.ptr, c->stream));
-                L.sobol_hi = (const uint32_t *)c->sobol_hi.ptr;
-            } else if (st == HESTON_OUT_OF_MEMORY || st == HESTON_OVER_BUDGET) {
+        const uint64_t extra = hi_bytes + (uint64_t)N * 4 + (uint64_t)N * 48;
+        const uint64_t held = c->sobol_hi.bytes + c->sobol_perm.bytes + c->sobol_dir12.bytes;
+        const bool fits = !c->budget || c->in_use - held + extra + 3 * 4096 <= c->budget;
+        std::vector<int32_t> node_of_pos;
+        std::vector<uint32_t> dir12;
+        bool fast = M % 64 == 0 && (first % M) % 64 == 0 && hi_bytes <= SOBOL_HI_MAX_BYTES && fits;
+        if (fast) {
+            if ((st = reserve(c, c->sobol_hi, hi_bytes)) == HESTON_OK &&
+                (st = reserve(c, c->sobol_perm, (size_t)N * 4)) == HESTON_OK)
+                st = reserve(c, c->sobol_dir12, (size_t)N * 48);
+            if (st == HESTON_OUT_OF_MEMORY || st == HESTON_OVER_BUDGET) {
                 g_last_error.clear();
-            } else {
+                fast = false;
+            } else if (st != HESTON_OK) {
                 return st;
             }
+        }
+        if (fast) {
+            node_of_pos.resize(N);
+            node_of_pos[0] = 0;
+            for (size_t k = 0; k < bp.ops.size(); ++k)
+                node_of_pos[k + 1] = bp.ops[k].node;
+            dir12.resize((size_t)N * 12);
+            for (uint32_t pos = 0; pos < N; ++pos)
+                for (uint32_t mm = 0; mm < 2; ++mm)
+                    for (uint32_t b = 0; b < 6; ++b)
+                        dir12[pos * 12 + mm * 6 + b] =
+                            o.sobol_directions[(size_t)(2 * node_of_pos[pos] + mm) * 32 + b];
+            HIP_TRY(hipMemcpyAsync(c->sobol_perm.ptr, node_of_pos.data(), (size_t)N * 4,
+                                   hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->sobol_dir12.ptr, dir12.data(), (size_t)N * 48,
+                                   hipMemcpyHostToDevice, c->stream));
+            const int32_t *perm = (const int32_t *)c->sobol_perm.ptr;
+            HIP_TRY(launch_sobol_shifts(q.seed, perm, dims, R, (uint32_t *)c->sobol_shift.ptr,
+                                        c->stream));
+            HIP_TRY(launch_sobol_hi((const uint32_t *)c->sobol_dirs.ptr, perm, dims, (uint32_t)n_blk,
+                                    (uint32_t *)c->sobol_hi.ptr, c->stream));
+            L.sobol_hi = (const uint32_t *)c->sobol_hi.ptr;
+            L.sobol_dir12 = (const uint32_t *)c->sobol_dir12.ptr;
+        } else {
+            HIP_TRY(launch_sobol_shifts(q.seed, nullptr, dims, R, (uint32_t *)c->sobol_shift.ptr,
+                                        c->stream));
         }
         HIP_TRY(hipMemcpyAsync(c->bridge_start.ptr, bp.start.data(), (q.n_steps + 1) * 4,
                                hipMemcpyHostToDevice, c->stream));
@@ -568,7 +601,7 @@ heston_status heston_ctx_destroy(heston_ctx *c)
         return fail(HESTON_INVALID_ARGUMENT, "ctx is NULL");
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift, &c->sobol_hi,
+    for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift, &c->sobol_hi, &c->sobol_perm, &c->sobol_dir12,
                       &c->bridge_start, &c->bridge_ops, &c->pay, &c->bump_partials,
                       &c->bump_sums, &c->step_w, &c->batch_opts, &c->batch_items, &c->batch_partials,
                       &c->batch_sums, &c->batch_counter, &c->batch_scratch})

@@ -66,9 +66,13 @@ struct PriceLaunch {
     StepCoef base, tup, tdn;        // grids of T, T + hT, T - hT
     // quasi-random
     const uint32_t *sobol_dirs;     // device [2N][32]
-    const uint32_t *sobol_shift;    // device [R][2N]
-    const uint32_t *sobol_hi;       // device [ceil(M/64)][2N] or null: per 64-point block,
-                                    // XOR of the direction numbers of Gray-code bits >= 6
+    const uint32_t *sobol_shift;    // device [R][2N] (position-ordered when sobol_dir12 is set)
+    const uint32_t *sobol_hi;       // device [ceil(M/64)][2N], position-ordered, or null: per
+                                    // 64-point block, XOR of the direction numbers of Gray-code
+                                    // bits >= 6
+    const uint32_t *sobol_dir12;    // device [N][12] or null: direction numbers 0..5 of the two
+                                    // dimensions of the node at each walk position (set exactly
+                                    // when sobol_hi is)
     const int32_t *bridge_start;    // device [N+1]: ops of step j are [start[j], start[j+1])
     const BridgeOp *bridge_ops;     // device [N-1]
     double bridge_root_scale;       // sqrt(N)
@@ -181,9 +185,12 @@ hipError_t launch_reduce(const PriceLaunch &L, double *rep_sums, hipStream_t str
 hipError_t launch_step_weights(const PriceLaunch &L, void *out, hipStream_t stream);
 
 // Writes the [reps][dims] digital shifts of the Sobol replicates of `seed`.
-hipError_t launch_sobol_hi(const uint32_t *dirs, uint32_t dims, uint32_t n_blk, uint32_t *out,
-                           hipStream_t stream);
-hipError_t launch_sobol_shifts(uint64_t seed, uint32_t dims, uint32_t reps, uint32_t *out,
+// perm (device [N], nullable): node of each walk position; with it the tables
+// are position-ordered (column 2 pos + m = dimension 2 perm[pos] + m).
+hipError_t launch_sobol_hi(const uint32_t *dirs, const int32_t *perm, uint32_t dims, uint32_t n_blk,
+                           uint32_t *out, hipStream_t stream);
+hipError_t launch_sobol_shifts(uint64_t seed, const int32_t *perm, uint32_t dims, uint32_t reps,
+                               uint32_t *out,
                                hipStream_t stream);
 
 } // namespace heston

@@ -18,6 +18,8 @@
 // in registers; Sobol normals come from direction numbers read through the
 // scalar cache and a Brownian-bridge stack in LDS.  Each block writes one FP64
 // partial record; a second kernel sums the partials in a fixed order.
+#include <type_traits>
+
 #include "device_math.hpp"
 #include "internal.hpp"
 #include "path_step.hpp"
@@ -227,71 +229,90 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         while (nbits < 30 && (M - 1) >> nbits)
             ++nbits;
         const uint32_t *shift = L.sobol_shift + (uint64_t)rep * 2u * N;
-        // When every wave covers 64 consecutive points starting at a multiple of
-        // 64, Gray-code bits 6 and up are the same in all its lanes: their XOR of
-        // direction numbers is wave-uniform (scalar), and each lane only combines
-        // six direction numbers under its fixed masks.
-        const bool aligned = (M % 64 == 0) && ((lo - rep_lo) % 64 == 0);
-        const uint32_t g_hi = __builtin_amdgcn_readfirstlane(g) & ~63u;
         uint32_t m[6];
 #pragma unroll
         for (int b = 0; b < 6; ++b)
             m[b] = 0u - ((g >> b) & 1u);
-        const uint32_t *hi_row =
-            L.sobol_hi ? L.sobol_hi + (uint64_t)(__builtin_amdgcn_readfirstlane((uint32_t)i) >> 6) * 2u * N
-                       : nullptr;
-        auto coord = [&](uint32_t d) -> uint32_t {
-            const uint32_t *v = L.sobol_dirs + 32u * d;
-            if (aligned) {
-                uint32_t u = shift[d];
-                if (hi_row != nullptr) {
-                    u ^= hi_row[d];
-                } else {
+        // Two walks.  Fast (the launch's waves cover 64-point-aligned blocks and
+        // the host built position-ordered tables): the node consumed at position
+        // pos (0 = root, o + 1 = bridge op o) reads the wave's row of the
+        // per-block table, the replicate's shift and its six low direction
+        // numbers of both dimensions at addresses that depend only on pos, so
+        // an op's loads do not wait on the op record.  Otherwise dimensions are
+        // addressed through the op's node index and each lane combines the
+        // direction numbers of its own Gray code.
+        auto walk = [&](auto fast_tag) {
+            constexpr bool FAST = decltype(fast_tag)::value;
+            const uint32_t *hi_row =
+                FAST ? L.sobol_hi + (uint64_t)(__builtin_amdgcn_readfirstlane((uint32_t)i) >> 6) * 2u * N
+                     : nullptr;
+            // When every wave covers 64 consecutive points starting at a multiple
+            // of 64, Gray-code bits 6 and up are the same in all its lanes: their
+            // XOR of direction numbers is wave-uniform (scalar), and each lane only
+            // combines six direction numbers under its fixed masks.
+            const bool aligned = (M % 64 == 0) && ((lo - rep_lo) % 64 == 0);
+            const uint32_t g_hi = __builtin_amdgcn_readfirstlane(g) & ~63u;
+            auto coord = [&](uint32_t d) -> uint32_t {
+                const uint32_t *v = L.sobol_dirs + 32u * d;
+                if (aligned) {
+                    uint32_t u = shift[d];
                     for (uint32_t bits = g_hi; bits; bits &= bits - 1)
                         u ^= v[__builtin_ctz(bits)];
+                    return u ^ sobol_low(v, m);
                 }
-                return u ^ sobol_low(v, m);
-            }
-            return sobol_coord(L.sobol_dirs, d, g, nbits, shift[d]);
-        };
-        auto node_normals = [&](int k, R &wa, R &wb) {
-            const uint32_t d = 2u * (uint32_t)k;
-            wa = sobol_normal<R>(coord(d));
-            wb = sobol_normal<R>(coord(d + 1));
-        };
-        R ca = 0, cbm = 0; // B_j of the two motions
-        {
-            R wa, wb;
-            node_normals(0, wa, wb);
-            const R sc = (R)L.bridge_root_scale;
-            slot(0, 0) = sc * wa;
-            slot(0, 1) = sc * wb;
-        }
-        int sp = 1;
-        for (uint32_t j = 0; j < N; ++j) {
-            const int op_end = L.bridge_start[j + 1];
-            for (int o = L.bridge_start[j]; o < op_end; ++o) {
-                const BridgeOp op = L.bridge_ops[o];
-                R wa, wb;
-                node_normals(op.node, wa, wb);
-                R a, b, c;
-                if constexpr (sizeof(R) == 4) {
-                    a = op.a; b = op.b; c = op.c;
+                return sobol_coord(L.sobol_dirs, d, g, nbits, shift[d]);
+            };
+            // normals of the node at walk position pos (node index k)
+            auto node_normals = [&](uint32_t pos, int k, R &wa, R &wb) {
+                if constexpr (FAST) {
+                    const uint32_t *v6 = L.sobol_dir12 + 12u * pos;
+                    const uint32_t c = 2u * pos;
+                    wa = sobol_normal<R>(shift[c] ^ hi_row[c] ^ sobol_low(v6, m));
+                    wb = sobol_normal<R>(shift[c + 1] ^ hi_row[c + 1] ^ sobol_low(v6 + 6, m));
                 } else {
-                    a = op.ad; b = op.bd; c = op.cd;
+                    const uint32_t d = 2u * (uint32_t)k;
+                    wa = sobol_normal<R>(coord(d));
+                    wb = sobol_normal<R>(coord(d + 1));
                 }
-                const R ta = slot(sp - 1, 0), tb = slot(sp - 1, 1);
-                slot(sp, 0) = a * ca + b * ta + c * wa;
-                slot(sp, 1) = a * cbm + b * tb + c * wb;
-                ++sp;
+            };
+            R ca = 0, cbm = 0; // B_j of the two motions
+            {
+                R wa, wb;
+                node_normals(0u, 0, wa, wb);
+                const R sc = (R)L.bridge_root_scale;
+                slot(0, 0) = sc * wa;
+                slot(0, 1) = sc * wb;
             }
-            --sp;
-            const R na = slot(sp, 0), nb = slot(sp, 1);
-            const R za = na - ca, zb = nb - cbm;
-            ca = na;
-            cbm = nb;
-            step(j, za, zb);
-        }
+            int sp = 1;
+            for (uint32_t j = 0; j < N; ++j) {
+                const int op_end = L.bridge_start[j + 1];
+                for (int o = L.bridge_start[j]; o < op_end; ++o) {
+                    const BridgeOp op = L.bridge_ops[o];
+                    R wa, wb;
+                    node_normals((uint32_t)o + 1u, op.node, wa, wb);
+                    R a, b, c;
+                    if constexpr (sizeof(R) == 4) {
+                        a = op.a; b = op.b; c = op.c;
+                    } else {
+                        a = op.ad; b = op.bd; c = op.cd;
+                    }
+                    const R ta = slot(sp - 1, 0), tb = slot(sp - 1, 1);
+                    slot(sp, 0) = a * ca + b * ta + c * wa;
+                    slot(sp, 1) = a * cbm + b * tb + c * wb;
+                    ++sp;
+                }
+                --sp;
+                const R na = slot(sp, 0), nb = slot(sp, 1);
+                const R za = na - ca, zb = nb - cbm;
+                ca = na;
+                cbm = nb;
+                step(j, za, zb);
+            }
+        };
+        if (L.sobol_dir12 != nullptr)
+            walk(std::true_type{});
+        else
+            walk(std::false_type{});
     }
 
     // ---- payoffs and Greek samples, in FP64 ----
@@ -512,31 +533,43 @@ __global__ void step_weights_kernel(uint32_t n, double r, double dt, double dt_u
     o[7] = (R)0;
 }
 
-// Per 64-point block b of a replicate and dimension d: the XOR of the
-// direction numbers v[d][k] over the set bits k >= 6 of the Gray code of
-// 64 b, which every point of the block shares (Gray code g(i) = i ^ (i >> 1)).
-__global__ void sobol_hi_kernel(const uint32_t *dirs, uint32_t dims, uint32_t n_blk, uint32_t *out)
+// Column c of the position-ordered tables holds dimension 2 node(c / 2) + c % 2,
+// where node(pos) is the bridge node consumed at walk position pos; without a
+// permutation column c is dimension c.
+__device__ __forceinline__ uint32_t table_dim(const int32_t *perm, uint32_t c)
+{
+    return perm ? 2u * (uint32_t)perm[c >> 1] + (c & 1u) : c;
+}
+
+// Per 64-point block b of a replicate and column c: the XOR of the direction
+// numbers v[d][k] of dimension d = table_dim(c) over the set bits k >= 6 of
+// the Gray code of 64 b, which every point of the block shares (Gray code
+// g(i) = i ^ (i >> 1)).
+__global__ void sobol_hi_kernel(const uint32_t *dirs, const int32_t *perm, uint32_t dims,
+                                uint32_t n_blk, uint32_t *out)
 {
     const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (uint64_t)dims * n_blk)
         return;
-    const uint32_t b = (uint32_t)(idx / dims), d = (uint32_t)(idx - (uint64_t)b * dims);
+    const uint32_t b = (uint32_t)(idx / dims), c = (uint32_t)(idx - (uint64_t)b * dims);
     const uint32_t i = b << 6;
-    const uint32_t *v = dirs + 32u * d;
+    const uint32_t *v = dirs + 32u * table_dim(perm, c);
     uint32_t x = 0;
     for (uint32_t bits = (i ^ (i >> 1)) & ~63u; bits; bits &= bits - 1)
         x ^= v[__builtin_ctz(bits)];
     out[idx] = x;
 }
 
-// Digital shifts of the Sobol replicates: shift[r][d] = top 30 bits of word 0
-// of Philox4x32-10(counter (d, r, 0, 1), key = seed).
-__global__ void sobol_shift_kernel(uint64_t seed, uint32_t dims, uint32_t reps, uint32_t *out)
+// Digital shifts of the Sobol replicates: shift[r][c] = top 30 bits of word 0
+// of Philox4x32-10(counter (d, r, 0, 1), key = seed), d = table_dim(c).
+__global__ void sobol_shift_kernel(uint64_t seed, const int32_t *perm, uint32_t dims, uint32_t reps,
+                                   uint32_t *out)
 {
     const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= dims * reps)
         return;
-    const uint32_t r = idx / dims, d = idx - r * dims;
+    const uint32_t r = idx / dims, c = idx - r * dims;
+    const uint32_t d = table_dim(perm, c);
     const U4 w = philox4x32_10(U4{d, r, 0u, 1u}, (uint32_t)seed, (uint32_t)(seed >> 32));
     out[idx] = w.x >> 2;
 }
@@ -589,21 +622,21 @@ hipError_t launch_step_weights(const PriceLaunch &L, void *out, hipStream_t stre
     return hipGetLastError();
 }
 
-hipError_t launch_sobol_hi(const uint32_t *dirs, uint32_t dims, uint32_t n_blk, uint32_t *out,
-                           hipStream_t stream)
+hipError_t launch_sobol_hi(const uint32_t *dirs, const int32_t *perm, uint32_t dims, uint32_t n_blk,
+                           uint32_t *out, hipStream_t stream)
 {
     const uint64_t n = (uint64_t)dims * n_blk;
     hipLaunchKernelGGL(sobol_hi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                       dirs, dims, n_blk, out);
+                       dirs, perm, dims, n_blk, out);
     return hipGetLastError();
 }
 
-hipError_t launch_sobol_shifts(uint64_t seed, uint32_t dims, uint32_t reps, uint32_t *out,
-                               hipStream_t stream)
+hipError_t launch_sobol_shifts(uint64_t seed, const int32_t *perm, uint32_t dims, uint32_t reps,
+                               uint32_t *out, hipStream_t stream)
 {
     const uint32_t n = dims * reps;
-    hipLaunchKernelGGL(sobol_shift_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, seed, dims,
-                       reps, out);
+    hipLaunchKernelGGL(sobol_shift_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, seed, perm,
+                       dims, reps, out);
     return hipGetLastError();
 }
 
