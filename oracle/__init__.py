@@ -7,7 +7,8 @@ Contents
 --------
 - ``heston_oracle.c`` (built to ``liboracle.so`` with gcc): Philox4x32-10, the
   Box-Muller normals, one Milstein path at a time in FP64 with its payoff and
-  pathwise estimators, and forward-mode derivatives of the payoff.
+  pathwise estimators, forward-mode derivatives of the payoff, and Andersen's
+  quadratic-exponential (QE) path.
 - this module: ctypes marshalling, plus the estimators built on top of the
   per-path records -- means and standard errors (two-pass), central
   bump-and-revalue Greeks on common random numbers by full re-simulation of
@@ -31,7 +32,7 @@ _SRC = os.path.join(_HERE, "heston_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT = 0, 1, 2, 3
-FULL_TRUNC, ABSORB = 0, 1
+FULL_TRUNC, ABSORB, QE = 0, 1, 2
 REC_FIELDS = ("S_T", "V_T", "Sbar", "pay", "pw_delta", "pw_rho")
 TAN_FIELDS = ("pay", "d_S0", "d_v0", "d_r", "d_kappa", "d_theta", "d_sigma", "d_rho",
               "max_dsqrt")
@@ -93,6 +94,8 @@ def lib():
         L.or_normals_block.restype = None
         L.or_uniform.argtypes = [ctypes.c_uint32]
         L.or_uniform.restype = ctypes.c_double
+        L.or_qe_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, dp, dp, dp]
+        L.or_qe_draws.restype = None
         _lib = L
     return _lib
 
@@ -132,8 +135,28 @@ def simulate(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int =
              n_paths: int = 1, mode: int = FULL_TRUNC, fixings=None, za=None, zb=None,
              threads: int = 1) -> np.ndarray:
     """Per-path records [n_paths, 6] = (S_T, V_T, Sbar, pay, pw_delta, pw_rho)."""
+    if mode == QE:
+        return simulate_qe(p, opt_type, n_steps, seed, first, n_paths, fixings, threads)[0]
     return _run("or_simulate", len(REC_FIELDS), p, opt_type, n_steps, seed, first, n_paths, mode,
                 fixings, za, zb, threads)
+
+
+def simulate_qe(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int = 0,
+                n_paths: int = 1, fixings=None, threads: int = 1):
+    """Andersen's QE scheme: (records [n_paths, 6] as simulate, margin [n_paths]), the
+    margin being the path's smallest distance from taking the other branch at a step:
+    |psi - 3/2| / (3/2), and |Uv - p| where the exponential branch is taken."""
+    out = _run("or_simulate", len(REC_FIELDS) + 1, p, opt_type, n_steps, seed, first, n_paths, QE,
+               fixings, None, None, threads)
+    return out[:, :len(REC_FIELDS)], out[:, len(REC_FIELDS)]
+
+
+def qe_draws(seed: int, path: int, step: int):
+    """The QE scheme's random inputs (Zs, Zv, Uv) of one step of one path."""
+    zs, zv, uv = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().or_qe_draws(seed & (2**64 - 1), path, step, ctypes.byref(zs), ctypes.byref(zv),
+                      ctypes.byref(uv))
+    return zs.value, zv.value, uv.value
 
 
 def tangent(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int = 0,

@@ -25,7 +25,15 @@
  *     the exact derivative of the discrete average);
  *   - forward-mode (tangent) derivatives of each path's discounted payoff with
  *     respect to (S0, v0, r, kappa, theta, sigma, rho), by the chain rule
- *     carried step by step alongside the path.
+ *     carried step by step alongside the path;
+ *   - Andersen's quadratic-exponential (QE) scheme (L. Andersen, "Simple and
+ *     efficient simulation of the Heston stochastic volatility model", Journal
+ *     of Computational Finance 11(3), 2008), the scheme the paper names as
+ *     future work: the variance is drawn from a moment-matched squared normal
+ *     or from a point mass at zero plus an exponential tail, and the log-price
+ *     step uses the start and end variances of the step (central weights
+ *     gamma1 = gamma2 = 1/2, switching level psi_c = 3/2, no martingale
+ *     correction).
  *
  * Readings taken where the paper is silent (stated again in the design notes):
  *   - integer step loop j = 0..N-1 with dt = T/N;
@@ -52,7 +60,8 @@ typedef struct {
 } or_params;
 
 enum { OR_EURO_CALL = 0, OR_EURO_PUT = 1, OR_ASIAN_CALL = 2, OR_ASIAN_PUT = 3 };
-enum { OR_FULL_TRUNC = 0, OR_ABSORB = 1 };
+enum { OR_FULL_TRUNC = 0, OR_ABSORB = 1, OR_QE = 2 };
+#define OR_REC_QE (OR_REC + 1) /* QE records add the path's smallest branch-decision margin */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (SC'11): ten rounds of two 32x32->64 multiplies, with the
@@ -131,6 +140,40 @@ static void step_normals(const or_source *src, uint64_t path, uint64_t row, uint
 static int is_asian(int type) { return type == OR_ASIAN_CALL || type == OR_ASIAN_PUT; }
 static int is_call(int type) { return type == OR_EURO_CALL || type == OR_ASIAN_CALL; }
 
+/* Discounted payoff and pathwise Delta / Rho of a finished path (S_T, V_T and
+ * the fixing sums A = sum S, B = sum t S); writes the first OR_REC values.    */
+static void finish_path(const or_params *P, int type, uint32_t n_fix, double S, double V, double A,
+                        double B, double *rec)
+{
+    const double D = exp(-P->r * P->T);
+    double Sbar = is_asian(type) ? A / (double)n_fix : S;
+    double pay, dpw, rpw;
+    if (is_call(type)) {
+        int itm = Sbar > P->K;
+        pay = D * (itm ? Sbar - P->K : 0.0);
+        dpw = itm ? D * Sbar / P->S0 : 0.0;
+        if (is_asian(type))
+            rpw = itm ? D * (B / (double)n_fix - P->T * (Sbar - P->K)) : 0.0;
+        else
+            rpw = itm ? D * P->K * P->T : 0.0;
+    } else {
+        int itm = Sbar < P->K;
+        pay = D * (itm ? P->K - Sbar : 0.0);
+        dpw = itm ? -D * Sbar / P->S0 : 0.0;
+        if (is_asian(type))
+            rpw = itm ? D * (-B / (double)n_fix - P->T * (P->K - Sbar)) : 0.0;
+        else
+            rpw = itm ? -D * P->K * P->T : 0.0;
+    }
+    rec[0] = S;
+    rec[1] = V;
+    rec[2] = Sbar;
+    rec[3] = pay;
+    rec[4] = dpw;
+    rec[5] = rpw;
+}
+
+
 /* One path of the Milstein scheme; writes the OR_REC record.
  * fix[j] != 0 marks step j (1..N) as an Asian fixing date; n_fix = |F|.     */
 static void sim_path(const or_params *P, int type, uint32_t N, const uint8_t *fix, uint32_t n_fix,
@@ -160,32 +203,98 @@ static void sim_path(const or_params *P, int type, uint32_t N, const uint8_t *fi
             B += t * S;
         }
     }
-    const double D = exp(-P->r * P->T);
-    double Sbar = is_asian(type) ? A / (double)n_fix : S;
-    double pay, dpw, rpw;
-    if (is_call(type)) {
-        int itm = Sbar > P->K;
-        pay = D * (itm ? Sbar - P->K : 0.0);
-        dpw = itm ? D * Sbar / P->S0 : 0.0;
-        if (is_asian(type))
-            rpw = itm ? D * (B / (double)n_fix - P->T * (Sbar - P->K)) : 0.0;
-        else
-            rpw = itm ? D * P->K * P->T : 0.0;
+    finish_path(P, type, n_fix, S, V, A, B, rec);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Andersen's QE scheme.  Random inputs of step j: one Philox4x32-10 block
+ * with counter (j, lo32 path, hi32 path, 4); words 0 and 1 give the
+ * Box-Muller pair (Zs drives the log-price, Zv the quadratic branch of the
+ * variance) and word 2 the uniform Uv of the exponential branch.            */
+#define OR_QE_PSI_C 1.5
+#define OR_QE_TAG 4u
+
+void or_qe_draws(uint64_t seed, uint64_t path, uint32_t step, double *zs, double *zv, double *uv)
+{
+    uint32_t ctr[4] = { step, (uint32_t)path, (uint32_t)(path >> 32), OR_QE_TAG };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t w[4];
+    or_philox4x32_10(ctr, key, w);
+    double ua = or_uniform(w[0]);
+    double ub = or_uniform(w[1]);
+    double radius = sqrt(-2.0 * log(ua));
+    double angle = 2.0 * M_PI * ub;
+    *zs = radius * cos(angle);
+    *zv = radius * sin(angle);
+    *uv = or_uniform(w[2]);
+}
+
+/* One step of the variance: the CIR conditional mean m and variance s2 of
+ * V(t+dt) given V(t) = V are matched either by a scaled squared normal
+ * (psi = s2/m^2 <= psi_c) or by a point mass at 0 with an exponential tail.
+ * *margin receives how close the step came to taking the other branch: the
+ * relative distance of psi from psi_c and, in the exponential branch, the
+ * distance of Uv from the mass p.                                            */
+static double qe_variance(const or_params *P, double dt, double V, double zv, double uv,
+                          double *margin)
+{
+    const double E = exp(-P->kappa * dt);
+    const double s2s = P->sigma * P->sigma;
+    const double m = P->theta + (V - P->theta) * E;
+    const double s2 = V * s2s * E * (1.0 - E) / P->kappa
+                      + P->theta * s2s * (1.0 - E) * (1.0 - E) / (2.0 * P->kappa);
+    const double psi = s2 / (m * m);
+    double mg = fabs(psi - OR_QE_PSI_C) / OR_QE_PSI_C;
+    double Vn;
+    if (psi <= OR_QE_PSI_C) {
+        const double inv = 2.0 / psi;
+        const double b2 = inv - 1.0 + sqrt(inv) * sqrt(inv - 1.0);
+        const double a = m / (1.0 + b2);
+        const double b = sqrt(b2);
+        Vn = a * (b + zv) * (b + zv);
     } else {
-        int itm = Sbar < P->K;
-        pay = D * (itm ? P->K - Sbar : 0.0);
-        dpw = itm ? -D * Sbar / P->S0 : 0.0;
-        if (is_asian(type))
-            rpw = itm ? D * (-B / (double)n_fix - P->T * (P->K - Sbar)) : 0.0;
-        else
-            rpw = itm ? -D * P->K * P->T : 0.0;
+        const double p = (psi - 1.0) / (psi + 1.0);
+        const double beta = (1.0 - p) / m;
+        Vn = (uv <= p) ? 0.0 : log((1.0 - p) / (1.0 - uv)) / beta;
+        if (fabs(uv - p) < mg)
+            mg = fabs(uv - p);
     }
-    rec[0] = S;
-    rec[1] = V;
-    rec[2] = Sbar;
-    rec[3] = pay;
-    rec[4] = dpw;
-    rec[5] = rpw;
+    *margin = mg;
+    return Vn;
+}
+
+/* One QE path; writes OR_REC values and, at rec[OR_REC], the smallest
+ * branch-decision margin of the path.                                        */
+static void sim_path_qe(const or_params *P, int type, uint32_t N, const uint8_t *fix,
+                        uint32_t n_fix, uint64_t seed, uint64_t path, double *rec)
+{
+    const double dt = P->T / (double)N;
+    const double g1 = 0.5, g2 = 0.5;
+    const double K0 = -P->rho * P->kappa * P->theta * dt / P->sigma;
+    const double K1 = g1 * dt * (P->kappa * P->rho / P->sigma - 0.5) - P->rho / P->sigma;
+    const double K2 = g2 * dt * (P->kappa * P->rho / P->sigma - 0.5) + P->rho / P->sigma;
+    const double K3 = g1 * dt * (1.0 - P->rho * P->rho);
+    const double K4 = g2 * dt * (1.0 - P->rho * P->rho);
+    double S = P->S0;
+    double V = P->v0;
+    double A = 0.0, B = 0.0;
+    double margin = INFINITY;
+    for (uint32_t j = 0; j < N; ++j) {
+        double zs, zv, uv, mg;
+        or_qe_draws(seed, path, j, &zs, &zv, &uv);
+        const double Vn = qe_variance(P, dt, V, zv, uv, &mg);
+        if (mg < margin)
+            margin = mg;
+        S = S * exp(P->r * dt + K0 + K1 * V + K2 * Vn + sqrt(K3 * V + K4 * Vn) * zs);
+        V = Vn;
+        if (fix[j + 1]) {
+            double t = (double)(j + 1) * dt;
+            A += S;
+            B += t * S;
+        }
+    }
+    finish_path(P, type, n_fix, S, V, A, B, rec);
+    rec[OR_REC] = margin;
 }
 
 /* Forward-mode derivatives of one path's discounted payoff with respect to
@@ -306,6 +415,9 @@ static void *run_job(void *arg)
         if (jb->tangent)
             tan_path(jb->P, jb->type, jb->N, jb->fix, jb->n_fix, jb->mode, jb->src, path, row,
                      jb->out + row * OR_TAN);
+        else if (jb->mode == OR_QE)
+            sim_path_qe(jb->P, jb->type, jb->N, jb->fix, jb->n_fix, jb->src->seed, path,
+                        jb->out + row * OR_REC_QE);
         else
             sim_path(jb->P, jb->type, jb->N, jb->fix, jb->n_fix, jb->mode, jb->src, path, row,
                      jb->out + row * OR_REC);
@@ -321,7 +433,12 @@ static int run(const or_params *P, int type, uint32_t N, const uint32_t *fix_ste
                int mode, uint64_t seed, uint64_t first, uint64_t n_paths, const double *za,
                const double *zb, int n_threads, int tangent, double *out)
 {
-    if (N == 0 || type < 0 || type > 3 || (mode != OR_FULL_TRUNC && mode != OR_ABSORB))
+    if (N == 0 || type < 0 || type > 3 ||
+        (mode != OR_FULL_TRUNC && mode != OR_ABSORB && mode != OR_QE))
+        return -1;
+    /* QE draws its own Philox inputs (no caller normals), needs sigma > 0 and
+     * theta > 0, and has no tangent path. */
+    if (mode == OR_QE && (za || zb || tangent || !(P->sigma > 0.0) || !(P->theta > 0.0)))
         return -1;
     uint8_t *fix = (uint8_t *)calloc((size_t)N + 1, 1);
     if (!fix)
