@@ -9,8 +9,8 @@ parameters only (nothing to stage); the timed region covers the library call.
 
 Prints ONE JSON line (rank 0).  Also reported: the roofline of the path kernel
 (an operation count per path-step against the FP32 vector peak), the Sobol +
-Brownian-bridge variant of the same step, the adjoint against plain
-bump-and-revalue, the 4096-option batch, the serving loop's latency, and the
+Brownian-bridge variant of the same step, the same step under the
+quadratic-exponential scheme, the adjoint against plain bump-and-revalue, the 4096-option batch, the serving loop's latency, and the
 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -58,8 +58,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="qmc,adjoint,batch,serve",
-                    help="extra legs reported after the timed steps: qmc, adjoint, batch, serve, "
+    ap.add_argument("--legs", default="qmc,qe,adjoint,batch,serve",
+                    help="extra legs reported after the timed steps: qmc, qe, adjoint, batch, serve, "
                          "and copy (a 256 MiB device copy that calibrates HBM byte counters)")
     return ap.parse_args()
 
@@ -289,6 +289,22 @@ def main():
         out["qmc_sobol_bridge"] = {"value": path_steps / (q_ms * 1e-3), "unit": "path-steps/s",
                                    "ms_per_step": q_ms, "kernel_ms": float(np.mean(qk)),
                                    "price": rq["price"], "replicates": QMC_REPLICATES}
+    if "qe" in legs:
+        # the same step under Andersen's QE scheme (one Philox block per step)
+        eopts = hm.Options(precision=hm.FP32, scheme=hm.QE)
+        for _ in range(2):
+            ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, eopts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ek = []
+        for _ in range(5):
+            re_ = ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, eopts)
+            ek.append(re_["device_ms"])
+        torch.cuda.synchronize()
+        e_ms = (time.perf_counter() - t1) / 5 * 1e3
+        out["qe_scheme"] = {"value": path_steps / (e_ms * 1e-3), "unit": "path-steps/s",
+                            "ms_per_step": e_ms, "kernel_ms": float(np.mean(ek)),
+                            "price": re_["price"]}
     if "adjoint" in legs:
         out["adjoint_vs_bump"] = adjoint_vs_bump(ctx, hm, torch)
     if "batch" in legs:

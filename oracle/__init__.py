@@ -143,12 +143,15 @@ def simulate(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int =
 
 def simulate_qe(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int = 0,
                 n_paths: int = 1, fixings=None, threads: int = 1):
-    """Andersen's QE scheme: (records [n_paths, 6] as simulate, margin [n_paths]), the
-    margin being the path's smallest distance from taking the other branch at a step:
-    |psi - 3/2| / (3/2), and |Uv - p| where the exponential branch is taken."""
-    out = _run("or_simulate", len(REC_FIELDS) + 1, p, opt_type, n_steps, seed, first, n_paths, QE,
+    """Andersen's QE scheme: (records [n_paths, 6] as simulate, margin [n_paths],
+    vscale [n_paths]).  margin is the path's smallest distance from taking the other
+    branch at a step: |psi - 3/2| / (3/2), and |Uv - p| where the exponential branch
+    is taken.  vscale is max_i V_i |dV_T/dV_i|, the sensitivity scale of the final
+    variance to relative perturbations of the variance along the path."""
+    n = len(REC_FIELDS)
+    out = _run("or_simulate", n + 2, p, opt_type, n_steps, seed, first, n_paths, QE,
                fixings, None, None, threads)
-    return out[:, :len(REC_FIELDS)], out[:, len(REC_FIELDS)]
+    return out[:, :n], out[:, n], out[:, n + 1]
 
 
 def qe_draws(seed: int, path: int, step: int):

@@ -61,7 +61,8 @@ typedef struct {
 
 enum { OR_EURO_CALL = 0, OR_EURO_PUT = 1, OR_ASIAN_CALL = 2, OR_ASIAN_PUT = 3 };
 enum { OR_FULL_TRUNC = 0, OR_ABSORB = 1, OR_QE = 2 };
-#define OR_REC_QE (OR_REC + 1) /* QE records add the path's smallest branch-decision margin */
+#define OR_REC_QE (OR_REC + 2) /* QE records add the path's smallest branch-decision margin and
+                                   the sensitivity scale of V_T (see sim_path_qe) */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (SC'11): ten rounds of two 32x32->64 multiplies, with the
@@ -263,8 +264,13 @@ static double qe_variance(const or_params *P, double dt, double V, double zv, do
     return Vn;
 }
 
-/* One QE path; writes OR_REC values and, at rec[OR_REC], the smallest
- * branch-decision margin of the path.                                        */
+/* One QE path; writes OR_REC values, at rec[OR_REC] the smallest
+ * branch-decision margin of the path, and at rec[OR_REC + 1] the sensitivity
+ * scale Q_N = max_i V_i |dV_N / dV_i| of the final variance to relative
+ * perturbations of the variance at earlier steps (Q_0 = V_0,
+ * Q_{j+1} = max(Q_j |D_j|, V_{j+1}), D_j = dV_{j+1}/dV_j by a central
+ * difference of the one-step map at fixed random inputs).  Rounding errors of
+ * a lower-precision evaluation of the same path grow with Q_N / V_N.         */
 static void sim_path_qe(const or_params *P, int type, uint32_t N, const uint8_t *fix,
                         uint32_t n_fix, uint64_t seed, uint64_t path, double *rec)
 {
@@ -279,12 +285,18 @@ static void sim_path_qe(const or_params *P, int type, uint32_t N, const uint8_t 
     double V = P->v0;
     double A = 0.0, B = 0.0;
     double margin = INFINITY;
+    double Q = V;
     for (uint32_t j = 0; j < N; ++j) {
-        double zs, zv, uv, mg;
+        double zs, zv, uv, mg, unused;
         or_qe_draws(seed, path, j, &zs, &zv, &uv);
         const double Vn = qe_variance(P, dt, V, zv, uv, &mg);
         if (mg < margin)
             margin = mg;
+        const double h = fmax(V * 1e-6, 1e-14);
+        const double D = (qe_variance(P, dt, V + h, zv, uv, &unused)
+                          - qe_variance(P, dt, fmax(V - h, 0.0), zv, uv, &unused))
+                         / (V + h - fmax(V - h, 0.0));
+        Q = fmax(Q * fabs(D), Vn);
         S = S * exp(P->r * dt + K0 + K1 * V + K2 * Vn + sqrt(K3 * V + K4 * Vn) * zs);
         V = Vn;
         if (fix[j + 1]) {
@@ -295,6 +307,7 @@ static void sim_path_qe(const or_params *P, int type, uint32_t N, const uint8_t 
     }
     finish_path(P, type, n_fix, S, V, A, B, rec);
     rec[OR_REC] = margin;
+    rec[OR_REC + 1] = Q;
 }
 
 /* Forward-mode derivatives of one path's discounted payoff with respect to

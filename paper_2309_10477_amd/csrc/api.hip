@@ -171,8 +171,14 @@ heston_status check_request(const Request &q)
         return fail(HESTON_INVALID_ARGUMENT, "unknown precision");
     if (o.rng != HESTON_RNG_PHILOX && o.rng != HESTON_RNG_SOBOL_BRIDGE)
         return fail(HESTON_INVALID_ARGUMENT, "unknown rng");
-    if (o.scheme != HESTON_FULL_TRUNCATION && o.scheme != HESTON_ABSORPTION)
+    if (o.scheme != HESTON_FULL_TRUNCATION && o.scheme != HESTON_ABSORPTION && o.scheme != HESTON_QE)
         return fail(HESTON_INVALID_ARGUMENT, "unknown scheme");
+    if (o.scheme == HESTON_QE) {
+        if (o.rng != HESTON_RNG_PHILOX)
+            return fail(HESTON_UNSUPPORTED, "the QE scheme draws Philox inputs only");
+        if (!(q.p.sigma > 0) || !(q.p.theta > 0))
+            return fail(HESTON_INVALID_ARGUMENT, "the QE scheme needs sigma > 0 and theta > 0");
+    }
     if (o.greeks & ~7u)
         return fail(HESTON_INVALID_ARGUMENT, "unknown greeks bits");
     if ((o.greeks & HESTON_GREEKS_BUMP_PLAIN) && (o.greeks & HESTON_GREEKS_BUMP_FUSED))
@@ -533,6 +539,8 @@ heston_status check_adjoint(const Request &q, uint32_t every, const void *ckpt, 
         return st;
     if (q.o.rng != HESTON_RNG_PHILOX)
         return fail(HESTON_UNSUPPORTED, "adjoint sensitivities need Philox normals");
+    if (q.o.scheme == HESTON_QE)
+        return fail(HESTON_UNSUPPORTED, "adjoint sensitivities follow the Milstein scheme");
     if (!(std::fabs(q.p.rho) < 1))
         return fail(HESTON_INVALID_ARGUMENT, "adjoint needs |rho| < 1");
     if (every != 8 && every != 16)

@@ -23,6 +23,8 @@ constexpr int N_ACC = 2 * N_EST;   // doubles per partial record
 constexpr int DUMP_WIDTH = 16;
 constexpr int BLOCK = 256;         // threads per block of the path kernels
 constexpr int MAX_BRIDGE_DEPTH = 24;
+// Fourth Philox counter word of the QE scheme's per-step block.
+constexpr uint32_t QE_COUNTER_TAG = 4u;
 // Largest per-block Sobol table (ceil(M/64) x 2N words) built for a launch;
 // above it the kernel combines the high direction numbers itself.
 constexpr uint64_t SOBOL_HI_MAX_BYTES = 256ull << 20;

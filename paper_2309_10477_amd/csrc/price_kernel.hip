@@ -132,9 +132,75 @@ __device__ __forceinline__ void scaled_step(R &y, R &w, const Grid<R> &g, R z1l,
         w = clamp0(w);
 }
 
-template <class R, int RNG, bool ASIAN, bool BUMPS, bool FT>
+// Andersen's quadratic-exponential (QE) scheme on one time grid, in the same
+// scaled state (y = ln(S/S0)/ln 2 without the drift r t, w = V dt).  With
+// E = e^{-kappa dt}, the square-root process's conditional mean and variance
+// of w' = V(t+dt) dt given w are m = E w + theta dt (1-E) and
+// s2 = cs1 w + cs0, cs1 = sigma^2 dt E (1-E) / kappa,
+// cs0 = theta sigma^2 dt^2 (1-E)^2 / (2 kappa); the log-price step is
+// (K0 + K1 V + K2 V' + sqrt(K3 V + K4 V') Zs) / ln 2 with Andersen's central
+// weights gamma1 = gamma2 = 1/2, here k0 = K0/ln 2, k1 = K1/(dt ln 2),
+// k2 = K2/(dt ln 2), k3 = K3/dt, k4 = K4/dt (the 1/ln 2 of the diffusion term
+// rides on Zs).
+template <class R> struct QEGrid {
+    R E, mth, cs1, cs0, k0, k1, k2, k3, k4;
+};
+
+template <class R> __device__ __forceinline__ QEGrid<R> qe_grid(const StepCoef &c, const PriceLaunch &L)
+{
+    const double dt = c.dt, E = exp(-L.kappa * dt), s2s = L.sigma * L.sigma;
+    const double kr = L.kappa * L.rho / L.sigma - 0.5;
+    QEGrid<R> g;
+    g.E = (R)E;
+    g.mth = (R)(L.theta * dt * (1.0 - E));
+    g.cs1 = (R)(s2s * dt * E * (1.0 - E) / L.kappa);
+    g.cs0 = (R)(L.theta * s2s * dt * dt * (1.0 - E) * (1.0 - E) / (2.0 * L.kappa));
+    g.k0 = (R)(-L.rho * L.kappa * L.theta * dt / L.sigma * LOG2E);
+    g.k1 = (R)((0.5 * dt * kr - L.rho / L.sigma) / dt * LOG2E);
+    g.k2 = (R)((0.5 * dt * kr + L.rho / L.sigma) / dt * LOG2E);
+    g.k3 = (R)(0.5 * (1.0 - L.rho * L.rho));
+    g.k4 = g.k3;
+    return g;
+}
+
+__device__ __forceinline__ float fast_log(float x) { return __builtin_amdgcn_logf(x) * (float)LN2; }
+__device__ __forceinline__ double fast_log(double x) { return log(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
+// One QE step of one scenario; z1l = Zs / ln 2, zv the normal of the
+// quadratic branch, uv the uniform of the exponential branch.  Both branches
+// are evaluated and one selected: psi = s2 / m^2 <= 3/2 takes the scaled
+// squared normal a (b + zv)^2, else V' is 0 with probability
+// p = (psi-1)/(psi+1) and exponential above it.
+template <class R>
+__device__ __forceinline__ void qe_step(R &y, R &w, const QEGrid<R> &g, R z1l, R zv, R uv)
+{
+    const R m = w * g.E + g.mth;
+    const R s2 = w * g.cs1 + g.cs0;
+    const R rm = fast_rcp(m);
+    const R psi = s2 * rm * rm;
+    // quadratic branch
+    const R inv = R(2) * m * m * fast_rcp(s2);
+    const R b2 = inv - R(1) + fast_sqrt(inv * (inv - R(1)));
+    const R b = fast_sqrt(b2);
+    const R a = m * fast_rcp(R(1) + b2);
+    const R bz = b + zv;
+    const R wq = a * bz * bz;
+    // exponential branch: 1 - p = 2 / (psi + 1), 1 / beta = m (psi + 1) / 2
+    const R pp1 = psi + R(1);
+    const R p = (psi - R(1)) * fast_rcp(pp1);
+    const R we = uv <= p ? R(0) : (R(0.5) * m * pp1) * fast_log(R(2) * fast_rcp(pp1 * (R(1) - uv)));
+    const R wn = psi <= R(1.5) ? wq : we;
+    y = y + g.k0 + g.k1 * w + g.k2 * wn + fast_sqrt(g.k3 * w + g.k4 * wn) * z1l;
+    w = wn;
+}
+
+template <class R, int RNG, bool ASIAN, bool BUMPS, int SCH>
 __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
 {
+    // SCH: 0 Milstein with full truncation, 1 Milstein with absorption, 2 QE
+    constexpr bool FT = SCH == 0;
     extern __shared__ unsigned char smem_raw[];
     __shared__ double red[BLOCK / 64][N_ACC];
 
@@ -161,25 +227,20 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         gu = grid<R>(L.tup, L.sigma);
         gd = grid<R>(L.tdn, L.sigma);
     }
-
-    // One step given the independent normals (za, zb) of step j.
-    auto step = [&](uint32_t j, R za, R zb) {
-        constexpr R FS = FT_SCALE<R, FT>;
-        const R z1l = za * (log2e * FS);
-        const R z2 = rho * za + rho_bar * zb;
-        const R z2m1 = z2 * z2 - R(1);
-        const R ab = gb.ktdt2 + gb.qdt2 * z2m1, sb = (gb.sdt * FS) * z2;
-        scaled_step<R, FT>(y, w, gb, z1l, ab, sb);
+    QEGrid<R> qb{}, qu{}, qd{};
+    if constexpr (SCH == 2) {
+        qb = qe_grid<R>(L.base, L);
         if constexpr (BUMPS) {
-            scaled_step<R, FT>(yv0, wv0, gb, z1l, ab, sb);
-            scaled_step<R, FT>(yv1, wv1, gb, z1l, ab, sb);
-            scaled_step<R, FT>(yt0, wt0, gu, z1l, gu.ktdt2 + gu.qdt2 * z2m1, (gu.sdt * FS) * z2);
-            scaled_step<R, FT>(yt1, wt1, gd, z1l, gd.ktdt2 + gd.qdt2 * z2m1, (gd.sdt * FS) * z2);
+            qu = qe_grid<R>(L.tup, L);
+            qd = qe_grid<R>(L.tdn, L);
         }
+    }
+
+    // Fixing sums after step j (the fixing at t = (j+1) dt): weights e^{rt},
+    // t e^{rt}, t^2 e^{rt}, t^3 e^{rt} (base grid), e^{rt} on the T +/- grids.
+    auto fixing = [&](uint32_t j) {
         if constexpr (ASIAN) {
             if (is_fixing(L.fix_bits, j + 1)) {
-                // weights of the fixing at t = (j+1) dt: e^{rt}, t e^{rt}, t^2 e^{rt},
-                // t^3 e^{rt} (base grid), e^{rt} on the T +/- grids
                 const R *tw = reinterpret_cast<const R *>(L.step_weights) + STEP_WEIGHTS * j;
                 const R e = exp2r(y);
                 A += tw[0] * e;
@@ -197,7 +258,50 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         }
     };
 
-    if constexpr (RNG == 0) {
+    // One Milstein step given the independent normals (za, zb) of step j.
+    auto step = [&](uint32_t j, R za, R zb) {
+        constexpr R FS = FT_SCALE<R, FT>;
+        const R z1l = za * (log2e * FS);
+        const R z2 = rho * za + rho_bar * zb;
+        const R z2m1 = z2 * z2 - R(1);
+        const R ab = gb.ktdt2 + gb.qdt2 * z2m1, sb = (gb.sdt * FS) * z2;
+        scaled_step<R, FT>(y, w, gb, z1l, ab, sb);
+        if constexpr (BUMPS) {
+            scaled_step<R, FT>(yv0, wv0, gb, z1l, ab, sb);
+            scaled_step<R, FT>(yv1, wv1, gb, z1l, ab, sb);
+            scaled_step<R, FT>(yt0, wt0, gu, z1l, gu.ktdt2 + gu.qdt2 * z2m1, (gu.sdt * FS) * z2);
+            scaled_step<R, FT>(yt1, wt1, gd, z1l, gd.ktdt2 + gd.qdt2 * z2m1, (gd.sdt * FS) * z2);
+        }
+        fixing(j);
+    };
+
+    if constexpr (SCH == 2) {
+        // QE: one Philox block per step, counter (j, lo32 p, hi32 p, 4); words 0, 1
+        // give the Box-Muller pair (Zs, Zv), word 2 the uniform Uv.
+        const uint32_t k0 = (uint32_t)L.seed, k1 = (uint32_t)(L.seed >> 32);
+        const uint32_t plo = (uint32_t)p, phi = L.wide_paths ? (uint32_t)(p >> 32) : 0u;
+        for (uint32_t j = 0; j < N; ++j) {
+            const U4 q = philox4x32_10(U4{j, plo, phi, QE_COUNTER_TAG}, k0, k1);
+            R zs, zv;
+            R uv;
+            if constexpr (sizeof(R) == 4) {
+                box_muller(uniform_f32(q.x), uniform_f32(q.y), zs, zv);
+                uv = uniform_f32(q.z);
+            } else {
+                box_muller(uniform_f64(q.x), uniform_f64(q.y), zs, zv);
+                uv = uniform_f64(q.z);
+            }
+            const R z1l = zs * log2e;
+            qe_step<R>(y, w, qb, z1l, zv, uv);
+            if constexpr (BUMPS) {
+                qe_step<R>(yv0, wv0, qb, z1l, zv, uv);
+                qe_step<R>(yv1, wv1, qb, z1l, zv, uv);
+                qe_step<R>(yt0, wt0, qu, z1l, zv, uv);
+                qe_step<R>(yt1, wt1, qd, z1l, zv, uv);
+            }
+            fixing(j);
+        }
+    } else if constexpr (RNG == 0) {
         // Philox: counter (j >> 1, lo32 p, hi32 p, 0); words (0,1) even step, (2,3) odd step.
         const uint32_t k0 = (uint32_t)L.seed, k1 = (uint32_t)(L.seed >> 32);
         // Paths below 2^32 have a zero high counter word: the first round's
@@ -574,20 +678,25 @@ __global__ void sobol_shift_kernel(uint64_t seed, const int32_t *perm, uint32_t 
     out[idx] = w.x >> 2;
 }
 
-template <class R, int RNG, bool ASIAN, bool BUMPS, bool FT>
+template <class R, int RNG, bool ASIAN, bool BUMPS, int SCH>
 hipError_t launch_t(const PriceLaunch &L, hipStream_t s)
 {
     const dim3 grid(L.blocks_per_rep, L.n_reps);
     const size_t smem = RNG == 1 ? (size_t)L.bridge_depth * 2 * BLOCK * sizeof(R) : 0;
-    hipLaunchKernelGGL((price_kernel<R, RNG, ASIAN, BUMPS, FT>), grid, dim3(BLOCK), smem, s, L);
+    hipLaunchKernelGGL((price_kernel<R, RNG, ASIAN, BUMPS, SCH>), grid, dim3(BLOCK), smem, s, L);
     return hipGetLastError();
 }
 
 template <class R, int RNG, bool ASIAN, bool BUMPS>
 hipError_t launch_ft(const PriceLaunch &L, hipStream_t s)
 {
-    return L.scheme == 0 ? launch_t<R, RNG, ASIAN, BUMPS, true>(L, s)
-                         : launch_t<R, RNG, ASIAN, BUMPS, false>(L, s);
+    if (L.scheme == 0)
+        return launch_t<R, RNG, ASIAN, BUMPS, 0>(L, s);
+    if (L.scheme == 1)
+        return launch_t<R, RNG, ASIAN, BUMPS, 1>(L, s);
+    if constexpr (RNG == 0)
+        return launch_t<R, RNG, ASIAN, BUMPS, 2>(L, s);
+    return hipErrorInvalidValue; // QE draws Philox inputs only (checked by the host)
 }
 
 template <class R, int RNG, bool ASIAN>

@@ -60,3 +60,25 @@ def test_struct_layout_matches_header():
     want = [ctypes.sizeof(hm.CParams), ctypes.sizeof(hm.COpts), ctypes.sizeof(hm.CResult),
             hm.COpts.fixing_steps.offset, hm.CResult.device_ms.offset]
     assert got == want
+
+
+def test_enum_constants_match_binding():
+    """The binding's constants are the header's values."""
+    import subprocess
+    import tempfile
+    import paper_2309_10477_amd as hm
+    names = ["HESTON_FP64", "HESTON_FP32", "HESTON_RNG_PHILOX", "HESTON_RNG_SOBOL_BRIDGE",
+             "HESTON_FULL_TRUNCATION", "HESTON_ABSORPTION", "HESTON_QE",
+             "HESTON_GREEKS_PATHWISE", "HESTON_GREEKS_BUMP_FUSED", "HESTON_GREEKS_BUMP_PLAIN"]
+    src = ('#include "heston.h"\n#include <stdio.h>\nint main(void){printf("'
+           + " ".join(["%d"] * len(names)) + '\\n", ' + ", ".join(f"(int){n}" for n in names)
+           + "); return 0;}\n")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "t")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        got = [int(v) for v in subprocess.check_output([exe]).split()]
+    want = [hm.FP64, hm.FP32, hm.PHILOX, hm.SOBOL_BRIDGE, hm.FULL_TRUNCATION, hm.ABSORPTION,
+            hm.QE, hm.GREEKS_PATHWISE, hm.GREEKS_BUMP_FUSED, hm.GREEKS_BUMP_PLAIN]
+    assert got == want

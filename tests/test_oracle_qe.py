@@ -33,7 +33,7 @@ def cir_transition(p, V, dt):
 
 def one_step(p, n, seed=3):
     """V after one QE step of length T from v0, for n paths."""
-    rec, _ = oracle.simulate_qe(p, EC, 1, seed, 0, n, threads=8)
+    rec, _, _ = oracle.simulate_qe(p, EC, 1, seed, 0, n, threads=8)
     return rec[:, 1]
 
 
@@ -97,8 +97,8 @@ def test_qe_european_matches_analytic(p):
     also where the Feller condition fails badly (second case)."""
     n = 400_000
     ref = analytic.heston_call(p)
-    r32, _ = oracle.simulate_qe(p, EC, 32, 11, 0, n, threads=8)
-    r16, _ = oracle.simulate_qe(p, EC, 16, 11, 0, n, threads=8)
+    r32, _, _ = oracle.simulate_qe(p, EC, 32, 11, 0, n, threads=8)
+    r16, _, _ = oracle.simulate_qe(p, EC, 16, 11, 0, n, threads=8)
     m32, se32 = oracle.mean_se(r32[:, 3])
     m16, _ = oracle.mean_se(r16[:, 3])
     assert abs(m32 - ref) < 3.5 * se32 + abs(m32 - m16)
@@ -108,7 +108,7 @@ def test_qe_martingale():
     """e^{-rT} E[S_T] = S0 within the statistical error (the scheme without the
     martingale correction leaves a bias far below it at these parameters)."""
     n = 400_000
-    rec, _ = oracle.simulate_qe(PB, EC, 24, 5, 0, n, threads=8)
+    rec, _, _ = oracle.simulate_qe(PB, EC, 24, 5, 0, n, threads=8)
     disc = math.exp(-PB.r * PB.T) * rec[:, 0]
     m, se = oracle.mean_se(disc)
     assert abs(m - PB.S0) < 4.0 * se
@@ -117,8 +117,8 @@ def test_qe_martingale():
 @pytest.mark.parametrize("asian", [False, True])
 def test_qe_put_call_identity_per_path(asian):
     """Same paths for the call and the put: C - P = D (X - K) on every path."""
-    c, _ = oracle.simulate_qe(PB, AC if asian else EC, 12, 4, 0, 2000)
-    q, _ = oracle.simulate_qe(PB, AP if asian else EP, 12, 4, 0, 2000)
+    c, _, _ = oracle.simulate_qe(PB, AC if asian else EC, 12, 4, 0, 2000)
+    q, _, _ = oracle.simulate_qe(PB, AP if asian else EP, 12, 4, 0, 2000)
     D = math.exp(-PB.r * PB.T)
     np.testing.assert_allclose(c[:, 3] - q[:, 3], D * (c[:, 2] - PB.K), rtol=0, atol=1e-12)
     np.testing.assert_array_equal(c[:, 0], q[:, 0])
@@ -129,3 +129,19 @@ def test_qe_rejects_unsupported_inputs():
         oracle.simulate_qe(PB.replace(sigma=0.0), EC, 4, 1, 0, 10)
     with pytest.raises(ValueError):
         oracle.simulate_qe(PB.replace(theta=0.0), EC, 4, 1, 0, 10)
+
+
+def test_variance_sensitivity_scale_bounds_a_whole_path_difference():
+    """vscale = max_i V_i |dV_T/dV_i| bounds the i = 0 term, which a central
+    difference of whole re-simulated paths in v0 measures directly; and it is
+    at least V_T itself."""
+    p = PB.replace(kappa=0.5, theta=0.02, sigma=1.0, v0=0.02)
+    n, N, h = 400, 12, 1e-6
+    rec, margin, vs = oracle.simulate_qe(p, EC, N, 21, 0, n)
+    up, _, _ = oracle.simulate_qe(p.replace(v0=p.v0 * (1 + h)), EC, N, 21, 0, n)
+    dn, _, _ = oracle.simulate_qe(p.replace(v0=p.v0 * (1 - h)), EC, N, 21, 0, n)
+    term0 = np.abs(up[:, 1] - dn[:, 1]) / (2 * h)  # v0 |dV_T/dv0|
+    ok = margin > 1e-3
+    assert ok.mean() > 0.5
+    assert (vs[ok] >= 0.999 * term0[ok] - 1e-12).all()
+    assert (vs >= rec[:, 1]).all()
