@@ -144,10 +144,10 @@ def simulate(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int =
 def simulate_qe(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int = 0,
                 n_paths: int = 1, fixings=None, threads: int = 1):
     """Andersen's QE scheme: (records [n_paths, 6] as simulate, margin [n_paths],
-    vscale [n_paths]).  margin is the path's smallest distance from taking the other
+    amp [n_paths]).  margin is the path's smallest distance from taking the other
     branch at a step: |psi - 3/2| / (3/2), and |Uv - p| where the exponential branch
-    is taken.  vscale is max_i V_i |dV_T/dV_i|, the sensitivity scale of the final
-    variance to relative perturbations of the variance along the path."""
+    is taken.  amp >= 1 is the path's amplification of relative variance errors:
+    max over j of max_{i<=j} V_i |dV_j/dV_i| / max(V_j, v0, theta)."""
     n = len(REC_FIELDS)
     out = _run("or_simulate", n + 2, p, opt_type, n_steps, seed, first, n_paths, QE,
                fixings, None, None, threads)

@@ -62,7 +62,7 @@ typedef struct {
 enum { OR_EURO_CALL = 0, OR_EURO_PUT = 1, OR_ASIAN_CALL = 2, OR_ASIAN_PUT = 3 };
 enum { OR_FULL_TRUNC = 0, OR_ABSORB = 1, OR_QE = 2 };
 #define OR_REC_QE (OR_REC + 2) /* QE records add the path's smallest branch-decision margin and
-                                   the sensitivity scale of V_T (see sim_path_qe) */
+                                   its amplification of variance errors (see sim_path_qe) */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (SC'11): ten rounds of two 32x32->64 multiplies, with the
@@ -265,12 +265,15 @@ static double qe_variance(const or_params *P, double dt, double V, double zv, do
 }
 
 /* One QE path; writes OR_REC values, at rec[OR_REC] the smallest
- * branch-decision margin of the path, and at rec[OR_REC + 1] the sensitivity
- * scale Q_N = max_i V_i |dV_N / dV_i| of the final variance to relative
- * perturbations of the variance at earlier steps (Q_0 = V_0,
- * Q_{j+1} = max(Q_j |D_j|, V_{j+1}), D_j = dV_{j+1}/dV_j by a central
- * difference of the one-step map at fixed random inputs).  Rounding errors of
- * a lower-precision evaluation of the same path grow with Q_N / V_N.         */
+ * branch-decision margin of the path, and at rec[OR_REC + 1] its
+ * amplification of relative variance errors,
+ *   a = max(1, max_j Q_j / max(V_j, v0, theta)),  Q_j = max_{i<=j} V_i |dV_j/dV_i|
+ * (Q_0 = V_0, Q_{j+1} = max(Q_j |D_j|, V_{j+1}), D_j = dV_{j+1}/dV_j by a
+ * central difference of the one-step map at fixed random inputs): how much a
+ * relative perturbation of the variance at one step can grow, in units of the
+ * path's variance scale, by any later step.  Every later log-price increment
+ * uses those variances, so rounding errors of a lower-precision evaluation of
+ * the same path grow in proportion.                                          */
 static void sim_path_qe(const or_params *P, int type, uint32_t N, const uint8_t *fix,
                         uint32_t n_fix, uint64_t seed, uint64_t path, double *rec)
 {
@@ -285,7 +288,8 @@ static void sim_path_qe(const or_params *P, int type, uint32_t N, const uint8_t 
     double V = P->v0;
     double A = 0.0, B = 0.0;
     double margin = INFINITY;
-    double Q = V;
+    double Q = V, amp = 1.0;
+    const double vscale = fmax(P->v0, P->theta);
     for (uint32_t j = 0; j < N; ++j) {
         double zs, zv, uv, mg, unused;
         or_qe_draws(seed, path, j, &zs, &zv, &uv);
@@ -297,6 +301,7 @@ static void sim_path_qe(const or_params *P, int type, uint32_t N, const uint8_t 
                           - qe_variance(P, dt, fmax(V - h, 0.0), zv, uv, &unused))
                          / (V + h - fmax(V - h, 0.0));
         Q = fmax(Q * fabs(D), Vn);
+        amp = fmax(amp, Q / fmax(Vn, vscale));
         S = S * exp(P->r * dt + K0 + K1 * V + K2 * Vn + sqrt(K3 * V + K4 * Vn) * zs);
         V = Vn;
         if (fix[j + 1]) {
@@ -307,7 +312,7 @@ static void sim_path_qe(const or_params *P, int type, uint32_t N, const uint8_t 
     }
     finish_path(P, type, n_fix, S, V, A, B, rec);
     rec[OR_REC] = margin;
-    rec[OR_REC + 1] = Q;
+    rec[OR_REC + 1] = amp;
 }
 
 /* Forward-mode derivatives of one path's discounted payoff with respect to

@@ -131,17 +131,17 @@ def test_qe_rejects_unsupported_inputs():
         oracle.simulate_qe(PB.replace(theta=0.0), EC, 4, 1, 0, 10)
 
 
-def test_variance_sensitivity_scale_bounds_a_whole_path_difference():
-    """vscale = max_i V_i |dV_T/dV_i| bounds the i = 0 term, which a central
-    difference of whole re-simulated paths in v0 measures directly; and it is
-    at least V_T itself."""
+def test_amplification_bounds_a_whole_path_difference():
+    """amp bounds, in units of the variance scale max(V_T, v0, theta), the growth of
+    a relative perturbation of v0 into V_T, which a central difference of whole
+    re-simulated paths in v0 measures directly."""
     p = PB.replace(kappa=0.5, theta=0.02, sigma=1.0, v0=0.02)
     n, N, h = 400, 12, 1e-6
-    rec, margin, vs = oracle.simulate_qe(p, EC, N, 21, 0, n)
+    rec, margin, amp = oracle.simulate_qe(p, EC, N, 21, 0, n)
     up, _, _ = oracle.simulate_qe(p.replace(v0=p.v0 * (1 + h)), EC, N, 21, 0, n)
     dn, _, _ = oracle.simulate_qe(p.replace(v0=p.v0 * (1 - h)), EC, N, 21, 0, n)
-    term0 = np.abs(up[:, 1] - dn[:, 1]) / (2 * h)  # v0 |dV_T/dv0|
+    growth = np.abs(up[:, 1] - dn[:, 1]) / (2 * h) / np.maximum(rec[:, 1], max(p.v0, p.theta))
     ok = margin > 1e-3
     assert ok.mean() > 0.5
-    assert (vs[ok] >= 0.999 * term0[ok] - 1e-12).all()
-    assert (vs >= rec[:, 1]).all()
+    assert (amp[ok] >= 0.999 * growth[ok] - 1e-9).all()
+    assert (amp >= 1.0).all() and amp.max() > 5.0
