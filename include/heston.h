@@ -75,7 +75,10 @@ enum { HESTON_FP64 = 0, HESTON_FP32 = 1 };
 enum { HESTON_RNG_PHILOX = 0, HESTON_RNG_SOBOL_BRIDGE = 1 };
 /* Scheme.  Milstein with full truncation (max(V,0) in drift and diffusion,
  * unclamped V carried) or with the paper's absorption (V <- max(V,0) after
- * every step, algorithm "Milstein approximation under Heston model"); or
+ * every step, algorithm "Milstein approximation under Heston model"); the
+ * paper's Euler discretisation (section "Euler discretisation": the same steps
+ * without the Milstein term sigma^2 dt (Z2^2 - 1) / 4) with either truncation;
+ * or
  * Andersen's quadratic-exponential scheme, which the paper names as future
  * work (L. Andersen, J. Computational Finance 11(3), 2008: the variance drawn
  * from a moment-matched squared normal or a point mass at zero with an
@@ -85,7 +88,13 @@ enum { HESTON_RNG_PHILOX = 0, HESTON_RNG_SOBOL_BRIDGE = 1 };
  * with counter (j, lo32 path, hi32 path, 4): Box-Muller of words 0, 1 for the
  * price and variance normals, word 2 for the exponential-branch uniform.
  * Adjoint calls, batches and the server use the Milstein schemes only. */
-enum { HESTON_FULL_TRUNCATION = 0, HESTON_ABSORPTION = 1, HESTON_QE = 2 };
+enum {
+    HESTON_FULL_TRUNCATION = 0,
+    HESTON_ABSORPTION = 1,
+    HESTON_QE = 2,
+    HESTON_EULER_FULL_TRUNCATION = 3,
+    HESTON_EULER_ABSORPTION = 4
+};
 /* Greek estimators (bit mask). */
 enum {
     HESTON_GREEKS_PATHWISE = 1u,   /* paper's pathwise Delta and Rho              */
@@ -123,7 +132,8 @@ typedef struct heston_opts {
     uint32_t struct_size; /* sizeof(heston_opts); set by heston_default_opts     */
     int32_t precision;    /* HESTON_FP64 (default) or HESTON_FP32                */
     int32_t rng;          /* HESTON_RNG_PHILOX (default) or HESTON_RNG_SOBOL_BRIDGE */
-    int32_t scheme;       /* HESTON_FULL_TRUNCATION (default), HESTON_ABSORPTION or HESTON_QE */
+    int32_t scheme;       /* HESTON_FULL_TRUNCATION (default), HESTON_ABSORPTION, HESTON_QE,
+                             HESTON_EULER_FULL_TRUNCATION or HESTON_EULER_ABSORPTION */
     uint32_t greeks;      /* HESTON_GREEKS_* mask; default PATHWISE | BUMP_FUSED */
     uint32_t qmc_replicates; /* Sobol: R digitally shifted replicates; n_paths must
                                 be a multiple of R (points per replicate = n_paths/R) */

@@ -26,6 +26,9 @@
  *   - forward-mode (tangent) derivatives of each path's discounted payoff with
  *     respect to (S0, v0, r, kappa, theta, sigma, rho), by the chain rule
  *     carried step by step alongside the path;
+ *   - the paper's Euler discretisation (Background, "Euler discretisation"):
+ *     the same log-price and variance steps without the Milstein term, with
+ *     either truncation;
  *   - Andersen's quadratic-exponential (QE) scheme (L. Andersen, "Simple and
  *     efficient simulation of the Heston stochastic volatility model", Journal
  *     of Computational Finance 11(3), 2008), the scheme the paper names as
@@ -60,7 +63,7 @@ typedef struct {
 } or_params;
 
 enum { OR_EURO_CALL = 0, OR_EURO_PUT = 1, OR_ASIAN_CALL = 2, OR_ASIAN_PUT = 3 };
-enum { OR_FULL_TRUNC = 0, OR_ABSORB = 1, OR_QE = 2 };
+enum { OR_FULL_TRUNC = 0, OR_ABSORB = 1, OR_QE = 2, OR_EULER_FULL_TRUNC = 3, OR_EULER_ABSORB = 4 };
 #define OR_REC_QE (OR_REC + 2) /* QE records add the path's smallest branch-decision margin and
                                    its amplification of variance errors (see sim_path_qe) */
 
@@ -175,11 +178,15 @@ static void finish_path(const or_params *P, int type, uint32_t n_fix, double S, 
 }
 
 
-/* One path of the Milstein scheme; writes the OR_REC record.
- * fix[j] != 0 marks step j (1..N) as an Asian fixing date; n_fix = |F|.     */
+/* One path of the Milstein scheme (or, in the Euler modes, of the Euler
+ * scheme: the variance step without the Milstein term); writes the OR_REC
+ * record.  fix[j] != 0 marks step j (1..N) as an Asian fixing date;
+ * n_fix = |F|.                                                              */
 static void sim_path(const or_params *P, int type, uint32_t N, const uint8_t *fix, uint32_t n_fix,
                      int mode, const or_source *src, uint64_t path, uint64_t row, double *rec)
 {
+    const int euler = mode == OR_EULER_FULL_TRUNC || mode == OR_EULER_ABSORB;
+    const int absorb = mode == OR_ABSORB || mode == OR_EULER_ABSORB;
     const double dt = P->T / (double)N;
     const double rho_bar = sqrt(1.0 - P->rho * P->rho);
     double S = P->S0;
@@ -193,10 +200,11 @@ static void sim_path(const or_params *P, int type, uint32_t N, const uint8_t *fi
         double z2 = P->rho * za + rho_bar * zb;
         double vp = V > 0.0 ? V : 0.0;
         S = S * exp((P->r - 0.5 * vp) * dt + sqrt(vp * dt) * z1);
-        double vb = (mode == OR_FULL_TRUNC) ? V : vp;
-        V = vb + P->kappa * (P->theta - vp) * dt + P->sigma * sqrt(vp * dt) * z2
-            + 0.25 * P->sigma * P->sigma * dt * (z2 * z2 - 1.0);
-        if (mode == OR_ABSORB && V < 0.0)
+        double vb = absorb ? vp : V;
+        V = vb + P->kappa * (P->theta - vp) * dt + P->sigma * sqrt(vp * dt) * z2;
+        if (!euler)
+            V += 0.25 * P->sigma * P->sigma * dt * (z2 * z2 - 1.0);
+        if (absorb && V < 0.0)
             V = 0.0;
         if (fix[j + 1]) {
             double t = (double)(j + 1) * dt;
@@ -451,9 +459,10 @@ static int run(const or_params *P, int type, uint32_t N, const uint32_t *fix_ste
                int mode, uint64_t seed, uint64_t first, uint64_t n_paths, const double *za,
                const double *zb, int n_threads, int tangent, double *out)
 {
-    if (N == 0 || type < 0 || type > 3 ||
-        (mode != OR_FULL_TRUNC && mode != OR_ABSORB && mode != OR_QE))
+    if (N == 0 || type < 0 || type > 3 || mode < OR_FULL_TRUNC || mode > OR_EULER_ABSORB)
         return -1;
+    if (tangent && mode != OR_FULL_TRUNC && mode != OR_ABSORB)
+        return -1; /* the tangent path follows the Milstein scheme */
     /* QE draws its own Philox inputs (no caller normals), needs sigma > 0 and
      * theta > 0, and has no tangent path. */
     if (mode == OR_QE && (za || zb || tangent || !(P->sigma > 0.0) || !(P->theta > 0.0)))

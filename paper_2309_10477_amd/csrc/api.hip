@@ -171,7 +171,7 @@ heston_status check_request(const Request &q)
         return fail(HESTON_INVALID_ARGUMENT, "unknown precision");
     if (o.rng != HESTON_RNG_PHILOX && o.rng != HESTON_RNG_SOBOL_BRIDGE)
         return fail(HESTON_INVALID_ARGUMENT, "unknown rng");
-    if (o.scheme != HESTON_FULL_TRUNCATION && o.scheme != HESTON_ABSORPTION && o.scheme != HESTON_QE)
+    if (o.scheme < HESTON_FULL_TRUNCATION || o.scheme > HESTON_EULER_ABSORPTION)
         return fail(HESTON_INVALID_ARGUMENT, "unknown scheme");
     if (o.scheme == HESTON_QE) {
         if (o.rng != HESTON_RNG_PHILOX)
@@ -230,7 +230,11 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
     L.kappa = p.kappa; L.theta = p.theta; L.sigma = p.sigma; L.rho = p.rho;
     L.rho_bar = std::sqrt(std::max(0.0, 1.0 - p.rho * p.rho));
     L.opt_type = q.type;
-    L.scheme = o.scheme;
+    // Euler is the Milstein kernel with the Milstein coefficient at zero.
+    const bool euler = o.scheme == HESTON_EULER_FULL_TRUNCATION || o.scheme == HESTON_EULER_ABSORPTION;
+    L.scheme = o.scheme == HESTON_EULER_FULL_TRUNCATION ? HESTON_FULL_TRUNCATION
+               : o.scheme == HESTON_EULER_ABSORPTION    ? HESTON_ABSORPTION
+                                                        : o.scheme;
     L.precision = o.precision;
     L.rng = o.rng;
     L.bumps = (o.greeks & HESTON_GREEKS_BUMP_FUSED) != 0;
@@ -240,6 +244,8 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
     L.n_paths = count;
     L.wide_paths = first + count > (1ull << 32);
     L.base = step_coef(p, p.T, q.n_steps);
+    if (euler)
+        L.base.quarter_sigma2_dt = 0.0;
     if (L.bumps) {
         L.hS = o.bump_S0_rel * p.S0;
         L.hv = o.bump_v0_rel * p.v0;
@@ -247,6 +253,8 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
         L.hT = o.bump_T_abs;
         L.tup = step_coef(p, p.T + L.hT, q.n_steps);
         L.tdn = step_coef(p, p.T - L.hT, q.n_steps);
+        if (euler)
+            L.tup.quarter_sigma2_dt = L.tdn.quarter_sigma2_dt = 0.0;
     }
     const bool asian = q.type >= 2;
     L.n_fix = asian ? (o.fixing_steps ? o.n_fixings : q.n_steps) : 1;
@@ -539,7 +547,7 @@ heston_status check_adjoint(const Request &q, uint32_t every, const void *ckpt, 
         return st;
     if (q.o.rng != HESTON_RNG_PHILOX)
         return fail(HESTON_UNSUPPORTED, "adjoint sensitivities need Philox normals");
-    if (q.o.scheme == HESTON_QE)
+    if (q.o.scheme != HESTON_FULL_TRUNCATION && q.o.scheme != HESTON_ABSORPTION)
         return fail(HESTON_UNSUPPORTED, "adjoint sensitivities follow the Milstein scheme");
     if (!(std::fabs(q.p.rho) < 1))
         return fail(HESTON_INVALID_ARGUMENT, "adjoint needs |rho| < 1");

@@ -69,6 +69,7 @@ def test_enum_constants_match_binding():
     import paper_2309_10477_amd as hm
     names = ["HESTON_FP64", "HESTON_FP32", "HESTON_RNG_PHILOX", "HESTON_RNG_SOBOL_BRIDGE",
              "HESTON_FULL_TRUNCATION", "HESTON_ABSORPTION", "HESTON_QE",
+             "HESTON_EULER_FULL_TRUNCATION", "HESTON_EULER_ABSORPTION",
              "HESTON_GREEKS_PATHWISE", "HESTON_GREEKS_BUMP_FUSED", "HESTON_GREEKS_BUMP_PLAIN"]
     src = ('#include "heston.h"\n#include <stdio.h>\nint main(void){printf("'
            + " ".join(["%d"] * len(names)) + '\\n", ' + ", ".join(f"(int){n}" for n in names)
@@ -80,5 +81,5 @@ def test_enum_constants_match_binding():
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     want = [hm.FP64, hm.FP32, hm.PHILOX, hm.SOBOL_BRIDGE, hm.FULL_TRUNCATION, hm.ABSORPTION,
-            hm.QE, hm.GREEKS_PATHWISE, hm.GREEKS_BUMP_FUSED, hm.GREEKS_BUMP_PLAIN]
+            hm.QE, hm.EULER_FULL_TRUNCATION, hm.EULER_ABSORPTION, hm.GREEKS_PATHWISE, hm.GREEKS_BUMP_FUSED, hm.GREEKS_BUMP_PLAIN]
     assert got == want

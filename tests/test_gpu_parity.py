@@ -61,7 +61,8 @@ def compare(name, g, o, tol, floor, allow=None):
 def check_records(dump, p, opt_type, n_steps, seed, first, count, prec, scheme, fixings, bumps,
                   za=None, zb=None, threads=8):
     tol = TOL[prec]
-    mode = oracle.ABSORB if scheme == 1 else oracle.FULL_TRUNC
+    mode = {0: oracle.FULL_TRUNC, 1: oracle.ABSORB, 3: oracle.EULER_FULL_TRUNC,
+            4: oracle.EULER_ABSORB}[scheme]
     rec = oracle.simulate(p, opt_type, n_steps, seed, first, count, mode, fixings, za, zb, threads)
     X = rec[:, 2]
     near = np.abs(X - p.K) < 1e3 * tol * p.K
@@ -103,11 +104,13 @@ def test_european_fp64_bumps_full_parity(hm, ctx):
 
 
 @pytest.mark.parametrize("opt_type", [0, 1, 2, 3])
-@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("scheme", [0, 1, 3, 4])
 def test_fp64_all_types_ragged(hm, ctx, opt_type, scheme):
+    """Milstein (0, 1) and the paper's Euler discretisation (3, 4), each under
+    full truncation and absorption."""
     n, N, seed = 1000 + 37, 7, 0xDEADBEEF12345
     fix = (2, 3, 7) if opt_type >= 2 else None
-    p = PP if scheme == 1 else PB
+    p = PP if scheme in (1, 4) else PB
     opts = hm.Options(scheme=scheme, fixings=fix)
     d = dump(hm, ctx, p, opt_type, n, N, seed, 0, n, opts)
     check_records(d, p, opt_type, N, seed, 0, n, 0, scheme, fix, True)
@@ -119,6 +122,27 @@ def test_fp32_all_types(hm, ctx, opt_type):
     opts = hm.Options(precision=hm.FP32)
     d = dump(hm, ctx, PB, opt_type, n, N, seed, 0, n, opts)
     check_records(d, PB, opt_type, N, seed, 0, n, 1, 0, None, True)
+
+
+@pytest.mark.parametrize("scheme", [3, 4])
+def test_euler_fp32(hm, ctx, scheme):
+    n, N, seed = 4096 + 100, 63, 9
+    opts = hm.Options(precision=hm.FP32, scheme=scheme)
+    d = dump(hm, ctx, PB, hm.ASIAN_PUT, n, N, seed, 0, n, opts)
+    check_records(d, PB, oracle.ASIAN_PUT, N, seed, 0, n, 1, scheme, None, True)
+
+
+def test_euler_rejected_by_adjoint_and_batch(hm, ctx):
+    import torch
+    opts = hm.Options(precision=hm.FP32, scheme=hm.EULER_FULL_TRUNCATION)
+    ck = torch.empty(hm.ckpt_bytes(256, 8, 8, hm.FP32), dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(hm.HestonError) as e:
+        ctx.adjoint_forward(PB.__dict__, 0, 256, 8, 1, ck, 8, opts)
+    assert e.value.status == -5
+    with pytest.raises(hm.HestonError) as e:
+        ctx.price_batch([dict(params=PB.__dict__, type=0, n_steps=4, n_paths=100, seed=1, want=1)],
+                        opts)
+    assert e.value.status == -5
 
 
 def test_asian_fp32_daily_fixings_252_steps(hm, ctx):
