@@ -32,7 +32,8 @@ _SRC = os.path.join(_HERE, "heston_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT = 0, 1, 2, 3
-FULL_TRUNC, ABSORB, QE, EULER_FULL_TRUNC, EULER_ABSORB = 0, 1, 2, 3, 4
+(FULL_TRUNC, ABSORB, QE, EULER_FULL_TRUNC, EULER_ABSORB, PARTIAL_TRUNC,
+ REFLECT) = 0, 1, 2, 3, 4, 5, 6
 REC_FIELDS = ("S_T", "V_T", "Sbar", "pay", "pw_delta", "pw_rho")
 TAN_FIELDS = ("pay", "d_S0", "d_v0", "d_r", "d_kappa", "d_theta", "d_sigma", "d_rho",
               "max_dsqrt")

@@ -29,6 +29,14 @@
  *   - the paper's Euler discretisation (Background, "Euler discretisation"):
  *     the same log-price and variance steps without the Milstein term, with
  *     either truncation;
+ *   - two more fixes of negative variances from Lord, Koekkoek and van Dijk,
+ *     "A comparison of biased simulation schemes for stochastic volatility
+ *     models", Quantitative Finance 10(2), 2010: writing the variance step as
+ *     V' = f1(V) + kappa (theta - f2(V)) dt + sigma sqrt(f3(V) dt) Z2 (+ the
+ *     Milstein term) and using f3 in the log-price step, partial truncation
+ *     takes f1 = f2 = identity, f3 = max(., 0), and reflection takes
+ *     f1 = f2 = f3 = |.| (full truncation: f1 = identity, f2 = f3 = max(., 0);
+ *     the paper's absorption: all max(., 0) and V' clamped);
  *   - Andersen's quadratic-exponential (QE) scheme (L. Andersen, "Simple and
  *     efficient simulation of the Heston stochastic volatility model", Journal
  *     of Computational Finance 11(3), 2008), the scheme the paper names as
@@ -63,7 +71,15 @@ typedef struct {
 } or_params;
 
 enum { OR_EURO_CALL = 0, OR_EURO_PUT = 1, OR_ASIAN_CALL = 2, OR_ASIAN_PUT = 3 };
-enum { OR_FULL_TRUNC = 0, OR_ABSORB = 1, OR_QE = 2, OR_EULER_FULL_TRUNC = 3, OR_EULER_ABSORB = 4 };
+enum {
+    OR_FULL_TRUNC = 0,
+    OR_ABSORB = 1,
+    OR_QE = 2,
+    OR_EULER_FULL_TRUNC = 3,
+    OR_EULER_ABSORB = 4,
+    OR_PARTIAL_TRUNC = 5,
+    OR_REFLECT = 6
+};
 #define OR_REC_QE (OR_REC + 2) /* QE records add the path's smallest branch-decision margin and
                                    its amplification of variance errors (see sim_path_qe) */
 
@@ -187,6 +203,8 @@ static void sim_path(const or_params *P, int type, uint32_t N, const uint8_t *fi
 {
     const int euler = mode == OR_EULER_FULL_TRUNC || mode == OR_EULER_ABSORB;
     const int absorb = mode == OR_ABSORB || mode == OR_EULER_ABSORB;
+    const int partial = mode == OR_PARTIAL_TRUNC;
+    const int reflect = mode == OR_REFLECT;
     const double dt = P->T / (double)N;
     const double rho_bar = sqrt(1.0 - P->rho * P->rho);
     double S = P->S0;
@@ -199,9 +217,13 @@ static void sim_path(const or_params *P, int type, uint32_t N, const uint8_t *fi
         double z1 = za;
         double z2 = P->rho * za + rho_bar * zb;
         double vp = V > 0.0 ? V : 0.0;
-        S = S * exp((P->r - 0.5 * vp) * dt + sqrt(vp * dt) * z1);
-        double vb = absorb ? vp : V;
-        V = vb + P->kappa * (P->theta - vp) * dt + P->sigma * sqrt(vp * dt) * z2;
+        double f1 = absorb ? vp : V, f2 = vp, f3 = vp;
+        if (partial)
+            f2 = V;
+        if (reflect)
+            f1 = f2 = f3 = fabs(V);
+        S = S * exp((P->r - 0.5 * f3) * dt + sqrt(f3 * dt) * z1);
+        V = f1 + P->kappa * (P->theta - f2) * dt + P->sigma * sqrt(f3 * dt) * z2;
         if (!euler)
             V += 0.25 * P->sigma * P->sigma * dt * (z2 * z2 - 1.0);
         if (absorb && V < 0.0)
@@ -459,7 +481,7 @@ static int run(const or_params *P, int type, uint32_t N, const uint32_t *fix_ste
                int mode, uint64_t seed, uint64_t first, uint64_t n_paths, const double *za,
                const double *zb, int n_threads, int tangent, double *out)
 {
-    if (N == 0 || type < 0 || type > 3 || mode < OR_FULL_TRUNC || mode > OR_EULER_ABSORB)
+    if (N == 0 || type < 0 || type > 3 || mode < OR_FULL_TRUNC || mode > OR_REFLECT)
         return -1;
     if (tangent && mode != OR_FULL_TRUNC && mode != OR_ABSORB)
         return -1; /* the tangent path follows the Milstein scheme */
