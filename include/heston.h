@@ -78,7 +78,11 @@ enum { HESTON_RNG_PHILOX = 0, HESTON_RNG_SOBOL_BRIDGE = 1 };
  * every step, algorithm "Milstein approximation under Heston model"); the
  * paper's Euler discretisation (section "Euler discretisation": the same steps
  * without the Milstein term sigma^2 dt (Z2^2 - 1) / 4) with either truncation;
- * or
+ * Milstein with partial truncation or reflection (Lord, Koekkoek, van Dijk,
+ * Quantitative Finance 10(2), 2010: in V' = f1(V) + kappa (theta - f2(V)) dt +
+ * sigma sqrt(f3(V) dt) Z2 + the Milstein term, with f3 also in the log-price
+ * step, partial truncation takes f1 = f2 = identity, f3 = max(., 0), and
+ * reflection f1 = f2 = f3 = |.|; the carried V is reported); or
  * Andersen's quadratic-exponential scheme, which the paper names as future
  * work (L. Andersen, J. Computational Finance 11(3), 2008: the variance drawn
  * from a moment-matched squared normal or a point mass at zero with an
@@ -93,7 +97,9 @@ enum {
     HESTON_ABSORPTION = 1,
     HESTON_QE = 2,
     HESTON_EULER_FULL_TRUNCATION = 3,
-    HESTON_EULER_ABSORPTION = 4
+    HESTON_EULER_ABSORPTION = 4,
+    HESTON_PARTIAL_TRUNCATION = 5,
+    HESTON_REFLECTION = 6
 };
 /* Greek estimators (bit mask). */
 enum {
@@ -133,7 +139,8 @@ typedef struct heston_opts {
     int32_t precision;    /* HESTON_FP64 (default) or HESTON_FP32                */
     int32_t rng;          /* HESTON_RNG_PHILOX (default) or HESTON_RNG_SOBOL_BRIDGE */
     int32_t scheme;       /* HESTON_FULL_TRUNCATION (default), HESTON_ABSORPTION, HESTON_QE,
-                             HESTON_EULER_FULL_TRUNCATION or HESTON_EULER_ABSORPTION */
+                             HESTON_EULER_FULL_TRUNCATION, HESTON_EULER_ABSORPTION,
+                             HESTON_PARTIAL_TRUNCATION or HESTON_REFLECTION */
     uint32_t greeks;      /* HESTON_GREEKS_* mask; default PATHWISE | BUMP_FUSED */
     uint32_t qmc_replicates; /* Sobol: R digitally shifted replicates; n_paths must
                                 be a multiple of R (points per replicate = n_paths/R) */

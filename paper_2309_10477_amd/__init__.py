@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libheston.so")
 EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 PHILOX, SOBOL_BRIDGE = 0, 1
-FULL_TRUNCATION, ABSORPTION, QE, EULER_FULL_TRUNCATION, EULER_ABSORPTION = 0, 1, 2, 3, 4
+(FULL_TRUNCATION, ABSORPTION, QE, EULER_FULL_TRUNCATION, EULER_ABSORPTION, PARTIAL_TRUNCATION,
+ REFLECTION) = 0, 1, 2, 3, 4, 5, 6
 GREEKS_PATHWISE, GREEKS_BUMP_FUSED, GREEKS_BUMP_PLAIN = 1, 2, 4
 DUMP_WIDTH = 16
 DUMP_FIELDS = ("S_T", "V_T", "Sbar", "pay", "pw_delta", "pw_rho", "pay_S0+", "pay_S0-",

@@ -171,7 +171,7 @@ heston_status check_request(const Request &q)
         return fail(HESTON_INVALID_ARGUMENT, "unknown precision");
     if (o.rng != HESTON_RNG_PHILOX && o.rng != HESTON_RNG_SOBOL_BRIDGE)
         return fail(HESTON_INVALID_ARGUMENT, "unknown rng");
-    if (o.scheme < HESTON_FULL_TRUNCATION || o.scheme > HESTON_EULER_ABSORPTION)
+    if (o.scheme < HESTON_FULL_TRUNCATION || o.scheme > HESTON_REFLECTION)
         return fail(HESTON_INVALID_ARGUMENT, "unknown scheme");
     if (o.scheme == HESTON_QE) {
         if (o.rng != HESTON_RNG_PHILOX)
@@ -232,9 +232,12 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
     L.opt_type = q.type;
     // Euler is the Milstein kernel with the Milstein coefficient at zero.
     const bool euler = o.scheme == HESTON_EULER_FULL_TRUNCATION || o.scheme == HESTON_EULER_ABSORPTION;
-    L.scheme = o.scheme == HESTON_EULER_FULL_TRUNCATION ? HESTON_FULL_TRUNCATION
-               : o.scheme == HESTON_EULER_ABSORPTION    ? HESTON_ABSORPTION
+    L.scheme = o.scheme == HESTON_EULER_FULL_TRUNCATION ? 0
+               : o.scheme == HESTON_EULER_ABSORPTION    ? 1
+               : o.scheme == HESTON_PARTIAL_TRUNCATION  ? 3
+               : o.scheme == HESTON_REFLECTION          ? 3
                                                         : o.scheme;
+    L.reflect = o.scheme == HESTON_REFLECTION;
     L.precision = o.precision;
     L.rng = o.rng;
     L.bumps = (o.greeks & HESTON_GREEKS_BUMP_FUSED) != 0;

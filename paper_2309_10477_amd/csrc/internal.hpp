@@ -49,7 +49,9 @@ struct PriceLaunch {
     // model and contract
     double S0, K, r, T, v0, kappa, theta, sigma, rho, rho_bar;
     int opt_type;      // heston_option_type
-    int scheme;        // 0 full truncation, 1 absorption
+    int scheme;        // kernel scheme: 0 full truncation, 1 absorption, 2 QE,
+                       // 3 partial truncation or reflection (see `reflect`)
+    bool reflect;      // scheme 3: reflection (else partial truncation)
     int precision;     // 0 fp64, 1 fp32
     int rng;           // 0 Philox, 1 Sobol + bridge
     bool bumps;        // fused bump scenarios

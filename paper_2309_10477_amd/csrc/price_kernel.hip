@@ -132,6 +132,27 @@ __device__ __forceinline__ void scaled_step(R &y, R &w, const Grid<R> &g, R z1l,
         w = clamp0(w);
 }
 
+// Partial truncation (reflect = false) and reflection (reflect = true) of the
+// variance, in the f1/f2/f3 form of Lord, Koekkoek and van Dijk (2010):
+// w' = f1(w) + (a_g - kappa dt f2(w)) + sqrt(f3(w)) s_g, with the log-price
+// step taking f3; partial truncation f1 = f2 = identity, f3 = max(., 0);
+// reflection f1 = f2 = f3 = |.|.  The choice is wave-uniform (a launch
+// parameter), so both variants share one kernel.
+template <class R>
+__device__ __forceinline__ void scaled_step_fix(R &y, R &w, const Grid<R> &g, R z1l, R a_g, R s_g,
+                                                bool reflect)
+{
+    constexpr R HALF_LOG2E = (R)(0.5 * LOG2E);
+    const R aw = fabs(w);
+    const R f12 = reflect ? aw : w;
+    const R f3 = reflect ? aw : clamp0(w);
+    const R s = fast_sqrt(f3);
+    y = y - HALF_LOG2E * f3;
+    y = y + s * z1l;
+    w = f12 + (a_g - g.kdt * f12);
+    w = w + s * s_g;
+}
+
 // Andersen's quadratic-exponential (QE) scheme on one time grid, in the same
 // scaled state (y = ln(S/S0)/ln 2 without the drift r t, w = V dt).  With
 // E = e^{-kappa dt}, the square-root process's conditional mean and variance
@@ -199,7 +220,8 @@ __device__ __forceinline__ void qe_step(R &y, R &w, const QEGrid<R> &g, R z1l, R
 template <class R, int RNG, bool ASIAN, bool BUMPS, int SCH>
 __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
 {
-    // SCH: 0 Milstein with full truncation, 1 Milstein with absorption, 2 QE
+    // SCH: 0 Milstein with full truncation, 1 Milstein with absorption, 2 QE,
+    // 3 Milstein with partial truncation or reflection (L.reflect)
     constexpr bool FT = SCH == 0;
     extern __shared__ unsigned char smem_raw[];
     __shared__ double red[BLOCK / 64][N_ACC];
@@ -265,12 +287,23 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         const R z2 = rho * za + rho_bar * zb;
         const R z2m1 = z2 * z2 - R(1);
         const R ab = gb.ktdt2 + gb.qdt2 * z2m1, sb = (gb.sdt * FS) * z2;
-        scaled_step<R, FT>(y, w, gb, z1l, ab, sb);
-        if constexpr (BUMPS) {
-            scaled_step<R, FT>(yv0, wv0, gb, z1l, ab, sb);
-            scaled_step<R, FT>(yv1, wv1, gb, z1l, ab, sb);
-            scaled_step<R, FT>(yt0, wt0, gu, z1l, gu.ktdt2 + gu.qdt2 * z2m1, (gu.sdt * FS) * z2);
-            scaled_step<R, FT>(yt1, wt1, gd, z1l, gd.ktdt2 + gd.qdt2 * z2m1, (gd.sdt * FS) * z2);
+        if constexpr (SCH == 3) {
+            const bool rf = L.reflect;
+            scaled_step_fix<R>(y, w, gb, z1l, ab, sb, rf);
+            if constexpr (BUMPS) {
+                scaled_step_fix<R>(yv0, wv0, gb, z1l, ab, sb, rf);
+                scaled_step_fix<R>(yv1, wv1, gb, z1l, ab, sb, rf);
+                scaled_step_fix<R>(yt0, wt0, gu, z1l, gu.ktdt2 + gu.qdt2 * z2m1, gu.sdt * z2, rf);
+                scaled_step_fix<R>(yt1, wt1, gd, z1l, gd.ktdt2 + gd.qdt2 * z2m1, gd.sdt * z2, rf);
+            }
+        } else {
+            scaled_step<R, FT>(y, w, gb, z1l, ab, sb);
+            if constexpr (BUMPS) {
+                scaled_step<R, FT>(yv0, wv0, gb, z1l, ab, sb);
+                scaled_step<R, FT>(yv1, wv1, gb, z1l, ab, sb);
+                scaled_step<R, FT>(yt0, wt0, gu, z1l, gu.ktdt2 + gu.qdt2 * z2m1, (gu.sdt * FS) * z2);
+                scaled_step<R, FT>(yt1, wt1, gd, z1l, gd.ktdt2 + gd.qdt2 * z2m1, (gd.sdt * FS) * z2);
+            }
         }
         fixing(j);
     };
@@ -694,6 +727,8 @@ hipError_t launch_ft(const PriceLaunch &L, hipStream_t s)
         return launch_t<R, RNG, ASIAN, BUMPS, 0>(L, s);
     if (L.scheme == 1)
         return launch_t<R, RNG, ASIAN, BUMPS, 1>(L, s);
+    if (L.scheme == 3)
+        return launch_t<R, RNG, ASIAN, BUMPS, 3>(L, s);
     if constexpr (RNG == 0)
         return launch_t<R, RNG, ASIAN, BUMPS, 2>(L, s);
     return hipErrorInvalidValue; // QE draws Philox inputs only (checked by the host)

@@ -70,6 +70,7 @@ def test_enum_constants_match_binding():
     names = ["HESTON_FP64", "HESTON_FP32", "HESTON_RNG_PHILOX", "HESTON_RNG_SOBOL_BRIDGE",
              "HESTON_FULL_TRUNCATION", "HESTON_ABSORPTION", "HESTON_QE",
              "HESTON_EULER_FULL_TRUNCATION", "HESTON_EULER_ABSORPTION",
+             "HESTON_PARTIAL_TRUNCATION", "HESTON_REFLECTION",
              "HESTON_GREEKS_PATHWISE", "HESTON_GREEKS_BUMP_FUSED", "HESTON_GREEKS_BUMP_PLAIN"]
     src = ('#include "heston.h"\n#include <stdio.h>\nint main(void){printf("'
            + " ".join(["%d"] * len(names)) + '\\n", ' + ", ".join(f"(int){n}" for n in names)
@@ -81,5 +82,6 @@ def test_enum_constants_match_binding():
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     want = [hm.FP64, hm.FP32, hm.PHILOX, hm.SOBOL_BRIDGE, hm.FULL_TRUNCATION, hm.ABSORPTION,
-            hm.QE, hm.EULER_FULL_TRUNCATION, hm.EULER_ABSORPTION, hm.GREEKS_PATHWISE, hm.GREEKS_BUMP_FUSED, hm.GREEKS_BUMP_PLAIN]
+            hm.QE, hm.EULER_FULL_TRUNCATION, hm.EULER_ABSORPTION, hm.PARTIAL_TRUNCATION,
+            hm.REFLECTION, hm.GREEKS_PATHWISE, hm.GREEKS_BUMP_FUSED, hm.GREEKS_BUMP_PLAIN]
     assert got == want

@@ -62,7 +62,7 @@ def check_records(dump, p, opt_type, n_steps, seed, first, count, prec, scheme, 
                   za=None, zb=None, threads=8):
     tol = TOL[prec]
     mode = {0: oracle.FULL_TRUNC, 1: oracle.ABSORB, 3: oracle.EULER_FULL_TRUNC,
-            4: oracle.EULER_ABSORB}[scheme]
+            4: oracle.EULER_ABSORB, 5: oracle.PARTIAL_TRUNC, 6: oracle.REFLECT}[scheme]
     rec = oracle.simulate(p, opt_type, n_steps, seed, first, count, mode, fixings, za, zb, threads)
     X = rec[:, 2]
     near = np.abs(X - p.K) < 1e3 * tol * p.K
@@ -104,13 +104,16 @@ def test_european_fp64_bumps_full_parity(hm, ctx):
 
 
 @pytest.mark.parametrize("opt_type", [0, 1, 2, 3])
-@pytest.mark.parametrize("scheme", [0, 1, 3, 4])
+@pytest.mark.parametrize("scheme", [0, 1, 3, 4, 5, 6])
 def test_fp64_all_types_ragged(hm, ctx, opt_type, scheme):
     """Milstein (0, 1) and the paper's Euler discretisation (3, 4), each under
-    full truncation and absorption."""
+    full truncation and absorption; Milstein with partial truncation (5) and
+    reflection (6), at a vol of vol that often turns the variance negative."""
     n, N, seed = 1000 + 37, 7, 0xDEADBEEF12345
     fix = (2, 3, 7) if opt_type >= 2 else None
     p = PP if scheme in (1, 4) else PB
+    if scheme in (5, 6):
+        p = PB.replace(v0=0.01, sigma=1.0, kappa=1.0, theta=0.02)
     opts = hm.Options(scheme=scheme, fixings=fix)
     d = dump(hm, ctx, p, opt_type, n, N, seed, 0, n, opts)
     check_records(d, p, opt_type, N, seed, 0, n, 0, scheme, fix, True)
@@ -124,17 +127,18 @@ def test_fp32_all_types(hm, ctx, opt_type):
     check_records(d, PB, opt_type, N, seed, 0, n, 1, 0, None, True)
 
 
-@pytest.mark.parametrize("scheme", [3, 4])
-def test_euler_fp32(hm, ctx, scheme):
+@pytest.mark.parametrize("scheme", [3, 4, 5, 6])
+def test_euler_and_fixes_fp32(hm, ctx, scheme):
     n, N, seed = 4096 + 100, 63, 9
     opts = hm.Options(precision=hm.FP32, scheme=scheme)
     d = dump(hm, ctx, PB, hm.ASIAN_PUT, n, N, seed, 0, n, opts)
     check_records(d, PB, oracle.ASIAN_PUT, N, seed, 0, n, 1, scheme, None, True)
 
 
-def test_euler_rejected_by_adjoint_and_batch(hm, ctx):
+@pytest.mark.parametrize("scheme", [3, 6])
+def test_non_milstein_truncations_rejected_by_adjoint_and_batch(hm, ctx, scheme):
     import torch
-    opts = hm.Options(precision=hm.FP32, scheme=hm.EULER_FULL_TRUNCATION)
+    opts = hm.Options(precision=hm.FP32, scheme=scheme)
     ck = torch.empty(hm.ckpt_bytes(256, 8, 8, hm.FP32), dtype=torch.uint8, device="cuda:0")
     with pytest.raises(hm.HestonError) as e:
         ctx.adjoint_forward(PB.__dict__, 0, 256, 8, 1, ck, 8, opts)
