@@ -31,7 +31,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "heston_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT = 0, 1, 2, 3
+EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT, GEO_ASIAN_CALL, GEO_ASIAN_PUT = 0, 1, 2, 3, 4, 5
 (FULL_TRUNC, ABSORB, QE, EULER_FULL_TRUNC, EULER_ABSORB, PARTIAL_TRUNC,
  REFLECT) = 0, 1, 2, 3, 4, 5, 6
 REC_FIELDS = ("S_T", "V_T", "Sbar", "pay", "pw_delta", "pw_rho")

@@ -70,7 +70,14 @@ typedef struct {
     double S0, K, r, T, v0, kappa, theta, sigma, rho;
 } or_params;
 
-enum { OR_EURO_CALL = 0, OR_EURO_PUT = 1, OR_ASIAN_CALL = 2, OR_ASIAN_PUT = 3 };
+enum {
+    OR_EURO_CALL = 0,
+    OR_EURO_PUT = 1,
+    OR_ASIAN_CALL = 2,
+    OR_ASIAN_PUT = 3,
+    OR_GEO_ASIAN_CALL = 4,
+    OR_GEO_ASIAN_PUT = 5
+};
 enum {
     OR_FULL_TRUNC = 0,
     OR_ABSORB = 1,
@@ -157,8 +164,27 @@ static void step_normals(const or_source *src, uint64_t path, uint64_t row, uint
     }
 }
 
-static int is_asian(int type) { return type == OR_ASIAN_CALL || type == OR_ASIAN_PUT; }
-static int is_call(int type) { return type == OR_EURO_CALL || type == OR_ASIAN_CALL; }
+/* Averaging types: arithmetic (the paper's) or geometric average of S over the
+ * fixing dates (the paper notes both are in use).                            */
+static int is_geo(int type) { return type == OR_GEO_ASIAN_CALL || type == OR_GEO_ASIAN_PUT; }
+static int is_asian(int type) { return type == OR_ASIAN_CALL || type == OR_ASIAN_PUT || is_geo(type); }
+static int is_call(int type)
+{
+    return type == OR_EURO_CALL || type == OR_ASIAN_CALL || type == OR_GEO_ASIAN_CALL;
+}
+
+/* Fixing-date sums: A = sum S and B = sum t S (arithmetic), or A = sum ln S
+ * and B = sum t (geometric).                                                 */
+static void add_fixing(int type, double S, double t, double *A, double *B)
+{
+    if (is_geo(type)) {
+        *A += log(S);
+        *B += t;
+    } else {
+        *A += S;
+        *B += t * S;
+    }
+}
 
 /* Discounted payoff and pathwise Delta / Rho of a finished path (S_T, V_T and
  * the fixing sums A = sum S, B = sum t S); writes the first OR_REC values.    */
@@ -166,7 +192,12 @@ static void finish_path(const or_params *P, int type, uint32_t n_fix, double S, 
                         double B, double *rec)
 {
     const double D = exp(-P->r * P->T);
-    double Sbar = is_asian(type) ? A / (double)n_fix : S;
+    const double nf = (double)n_fix;
+    double Sbar = is_geo(type) ? exp(A / nf) : is_asian(type) ? A / nf : S;
+    /* B / n_fix becomes dSbar/dr: the average of t S (arithmetic), or
+     * G times the average fixing time (geometric).                           */
+    if (is_geo(type))
+        B = Sbar * B;
     double pay, dpw, rpw;
     if (is_call(type)) {
         int itm = Sbar > P->K;
@@ -228,11 +259,8 @@ static void sim_path(const or_params *P, int type, uint32_t N, const uint8_t *fi
             V += 0.25 * P->sigma * P->sigma * dt * (z2 * z2 - 1.0);
         if (absorb && V < 0.0)
             V = 0.0;
-        if (fix[j + 1]) {
-            double t = (double)(j + 1) * dt;
-            A += S;
-            B += t * S;
-        }
+        if (fix[j + 1])
+            add_fixing(type, S, (double)(j + 1) * dt, &A, &B);
     }
     finish_path(P, type, n_fix, S, V, A, B, rec);
 }
@@ -334,11 +362,8 @@ static void sim_path_qe(const or_params *P, int type, uint32_t N, const uint8_t 
         amp = fmax(amp, Q / fmax(Vn, vscale));
         S = S * exp(P->r * dt + K0 + K1 * V + K2 * Vn + sqrt(K3 * V + K4 * Vn) * zs);
         V = Vn;
-        if (fix[j + 1]) {
-            double t = (double)(j + 1) * dt;
-            A += S;
-            B += t * S;
-        }
+        if (fix[j + 1])
+            add_fixing(type, S, (double)(j + 1) * dt, &A, &B);
     }
     finish_path(P, type, n_fix, S, V, A, B, rec);
     rec[OR_REC] = margin;
@@ -481,8 +506,10 @@ static int run(const or_params *P, int type, uint32_t N, const uint32_t *fix_ste
                int mode, uint64_t seed, uint64_t first, uint64_t n_paths, const double *za,
                const double *zb, int n_threads, int tangent, double *out)
 {
-    if (N == 0 || type < 0 || type > 3 || mode < OR_FULL_TRUNC || mode > OR_REFLECT)
+    if (N == 0 || type < 0 || type > OR_GEO_ASIAN_PUT || mode < OR_FULL_TRUNC || mode > OR_REFLECT)
         return -1;
+    if (tangent && is_geo(type))
+        return -1; /* the tangent path covers the European and arithmetic payoffs */
     if (tangent && mode != OR_FULL_TRUNC && mode != OR_ABSORB)
         return -1; /* the tangent path follows the Milstein scheme */
     /* QE draws its own Philox inputs (no caller normals), needs sigma > 0 and
