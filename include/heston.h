@@ -50,12 +50,17 @@ typedef struct heston_params {
     double S0, K, r, T, v0, kappa, theta, sigma, rho;
 } heston_params;
 
-/* Payoffs (paper: Background, European and arithmetic-Asian payoffs). */
+/* Payoffs (paper: Background, European and arithmetic-Asian payoffs; the
+ * paper notes the average may also be geometric: G = exp(mean of ln S over the
+ * fixing dates)).  Geometric averages are priced by the pricing calls only
+ * (not by adjoint calls, batches or the server). */
 typedef enum heston_option_type {
     HESTON_EURO_CALL = 0,
     HESTON_EURO_PUT = 1,
     HESTON_ASIAN_CALL = 2,
-    HESTON_ASIAN_PUT = 3
+    HESTON_ASIAN_PUT = 3,
+    HESTON_GEO_ASIAN_CALL = 4,
+    HESTON_GEO_ASIAN_PUT = 5
 } heston_option_type;
 
 typedef enum heston_status {

@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libheston.so")
 
-EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT = 0, 1, 2, 3
+EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT, GEO_ASIAN_CALL, GEO_ASIAN_PUT = 0, 1, 2, 3, 4, 5
 FP64, FP32 = 0, 1
 PHILOX, SOBOL_BRIDGE = 0, 1
 (FULL_TRUNCATION, ABSORPTION, QE, EULER_FULL_TRUNCATION, EULER_ABSORPTION, PARTIAL_TRUNCATION,

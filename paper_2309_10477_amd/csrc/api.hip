@@ -158,7 +158,7 @@ heston_status check_request(const Request &q)
     heston_status st = check_params(&q.p);
     if (st != HESTON_OK)
         return st;
-    if (q.type < 0 || q.type > 3)
+    if (q.type < 0 || q.type > HESTON_GEO_ASIAN_PUT)
         return fail(HESTON_INVALID_ARGUMENT, "unknown option type");
     if (q.n_paths < 2)
         return fail(HESTON_INVALID_ARGUMENT, "need n_paths >= 2");
@@ -260,7 +260,15 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
             L.tup.quarter_sigma2_dt = L.tdn.quarter_sigma2_dt = 0.0;
     }
     const bool asian = q.type >= 2;
+    const bool geo = q.type == HESTON_GEO_ASIAN_CALL || q.type == HESTON_GEO_ASIAN_PUT;
     L.n_fix = asian ? (o.fixing_steps ? o.n_fixings : q.n_steps) : 1;
+    // sum of the fixing step indices: the fixing times sum to dt times it
+    L.fix_step_sum = 0.0;
+    if (o.fixing_steps)
+        for (uint32_t i = 0; i < o.n_fixings; ++i)
+            L.fix_step_sum += (double)o.fixing_steps[i];
+    else
+        L.fix_step_sum = 0.5 * (double)q.n_steps * ((double)q.n_steps + 1.0);
     L.fix_bits = nullptr;
     if (asian && o.fixing_steps) {
         const size_t words = (q.n_steps + 1 + 31) / 32;
@@ -275,7 +283,7 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
         HIP_TRY(hipStreamSynchronize(c->stream)); // `bits` is released at return
         L.fix_bits = (const uint32_t *)c->fix_bits.ptr;
     }
-    if (asian) {
+    if (asian && !geo) {
         const size_t real = o.precision == HESTON_FP64 ? 8 : 4;
         heston_status st = reserve(c, c->step_w, (size_t)q.n_steps * STEP_WEIGHTS * real);
         if (st != HESTON_OK)
@@ -552,6 +560,8 @@ heston_status check_adjoint(const Request &q, uint32_t every, const void *ckpt, 
         return fail(HESTON_UNSUPPORTED, "adjoint sensitivities need Philox normals");
     if (q.o.scheme != HESTON_FULL_TRUNCATION && q.o.scheme != HESTON_ABSORPTION)
         return fail(HESTON_UNSUPPORTED, "adjoint sensitivities follow the Milstein scheme");
+    if (q.type > HESTON_ASIAN_PUT)
+        return fail(HESTON_UNSUPPORTED, "adjoint sensitivities cover European and arithmetic-Asian payoffs");
     if (!(std::fabs(q.p.rho) < 1))
         return fail(HESTON_INVALID_ARGUMENT, "adjoint needs |rho| < 1");
     if (every != 8 && every != 16)

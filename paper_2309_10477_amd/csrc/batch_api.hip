@@ -24,6 +24,8 @@ heston_status check_batch_request(const heston_request &r, const heston_opts &o,
     heston_status st = check_request(q);
     if (st != HESTON_OK)
         return st;
+    if (r.type > HESTON_ASIAN_PUT)
+        return fail(HESTON_UNSUPPORTED, "batches price European and arithmetic-Asian payoffs");
     if (r.want != HESTON_WANT_PATHWISE && r.want != HESTON_WANT_ADJOINT)
         return fail(HESTON_INVALID_ARGUMENT, "want must be WANT_PATHWISE or WANT_ADJOINT");
     if (r.want == HESTON_WANT_ADJOINT && !(std::fabs(r.params.rho) < 1))

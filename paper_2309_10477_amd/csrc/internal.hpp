@@ -57,6 +57,7 @@ struct PriceLaunch {
     bool bumps;        // fused bump scenarios
     uint32_t n_steps;
     uint32_t n_fix;                 // number of fixing dates
+    double fix_step_sum;            // sum of the fixing step indices (fixing times / dt)
     const uint32_t *fix_bits;       // device bitmask over steps 1..N (bit j), or null = every step
     uint64_t seed;
     uint64_t first_path;            // first path handled by the launch

@@ -30,7 +30,7 @@ namespace {
 struct Payoff {
     int type;
     double K, inv_nfix;
-    __device__ __forceinline__ bool call() const { return type == 0 || type == 2; }
+    __device__ __forceinline__ bool call() const { return type == 0 || type == 2 || type == 4; }
     __device__ __forceinline__ double operator()(double D, double X) const
     {
         const double in = call() ? X - K : K - X;
@@ -217,11 +217,13 @@ __device__ __forceinline__ void qe_step(R &y, R &w, const QEGrid<R> &g, R z1l, R
     w = wn;
 }
 
-template <class R, int RNG, bool ASIAN, bool BUMPS, int SCH>
+template <class R, int RNG, int AV, bool BUMPS, int SCH>
 __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
 {
+    // AV: 0 European, 1 arithmetic average, 2 geometric average over the fixings.
     // SCH: 0 Milstein with full truncation, 1 Milstein with absorption, 2 QE,
     // 3 Milstein with partial truncation or reflection (L.reflect)
+    constexpr bool ASIAN = AV != 0, GEO = AV == 2;
     constexpr bool FT = SCH == 0;
     extern __shared__ unsigned char smem_raw[];
     __shared__ double red[BLOCK / 64][N_ACC];
@@ -261,7 +263,18 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
     // Fixing sums after step j (the fixing at t = (j+1) dt): weights e^{rt},
     // t e^{rt}, t^2 e^{rt}, t^3 e^{rt} (base grid), e^{rt} on the T +/- grids.
     auto fixing = [&](uint32_t j) {
-        if constexpr (ASIAN) {
+        if constexpr (GEO) {
+            // geometric average: the same registers sum each scenario's y
+            if (is_fixing(L.fix_bits, j + 1)) {
+                A += y;
+                if constexpr (BUMPS) {
+                    Av0 += yv0;
+                    Av1 += yv1;
+                    At0 += yt0;
+                    At1 += yt1;
+                }
+            }
+        } else if constexpr (ASIAN) {
             if (is_fixing(L.fix_bits, j + 1)) {
                 const R *tw = reinterpret_cast<const R *>(L.step_weights) + STEP_WEIGHTS * j;
                 const R e = exp2r(y);
@@ -459,14 +472,22 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
     const double x = (double)y * LN2 + L.r * L.T;
     const double eT = exp(x);
     const double ST = S0 * eT;
-    const double rel = ASIAN ? (double)A * pay.inv_nfix : eT; // Sbar / S0 (or S_T / S0)
+    // geometric averages: the fixing times of each grid sum to dt times the
+    // sum of the fixing step indices; G / S0 = exp(mean of (y ln 2 + r t_i))
+    const double tsum = L.base.dt * L.fix_step_sum;
+    auto geo_rel = [&](double ysum, double ts) {
+        return exp(((double)ysum * LN2 + L.r * ts) * pay.inv_nfix);
+    };
+    // Sbar / S0 (or G / S0, or S_T / S0), and the dSbar/dr term of the pathwise Rho
+    const double rel = GEO ? geo_rel((double)A, tsum) : ASIAN ? (double)A * pay.inv_nfix : eT;
+    const double dBr = GEO ? rel * tsum : (double)B;
     const double X = S0 * rel;
     const double sgn = pay.call() ? 1.0 : -1.0;
     const bool itm = sgn * (X - L.K) > 0.0;
     est[EST_PRICE] = pay(D, X);
     est[EST_PW_DELTA] = itm ? sgn * D * rel : 0.0;
     if (ASIAN)
-        est[EST_PW_RHO] = itm ? D * (sgn * S0 * (double)B * pay.inv_nfix - L.T * sgn * (X - L.K)) : 0.0;
+        est[EST_PW_RHO] = itm ? D * (sgn * S0 * dBr * pay.inv_nfix - L.T * sgn * (X - L.K)) : 0.0;
     else
         est[EST_PW_RHO] = itm ? sgn * D * L.K * L.T : 0.0;
 
@@ -475,13 +496,22 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         const double hS = L.hS, hr = L.hr;
         sc[0] = pay(D, (S0 + hS) * rel);
         sc[1] = pay(D, (S0 - hS) * rel);
-        const double Xv0 = S0 * (ASIAN ? (double)Av0 * pay.inv_nfix : exp((double)yv0 * LN2 + L.r * L.T));
-        const double Xv1 = S0 * (ASIAN ? (double)Av1 * pay.inv_nfix : exp((double)yv1 * LN2 + L.r * L.T));
+        const double Xv0 = S0 * (GEO     ? geo_rel((double)Av0, tsum)
+                                 : ASIAN ? (double)Av0 * pay.inv_nfix
+                                         : exp((double)yv0 * LN2 + L.r * L.T));
+        const double Xv1 = S0 * (GEO     ? geo_rel((double)Av1, tsum)
+                                 : ASIAN ? (double)Av1 * pay.inv_nfix
+                                         : exp((double)yv1 * LN2 + L.r * L.T));
         sc[2] = pay(D, Xv0);
         sc[3] = pay(D, Xv1);
         const double Dup = exp(-(L.r + hr) * L.T), Ddn = exp(-(L.r - hr) * L.T);
         double Xu, Xd;
-        if (ASIAN) {
+        if (GEO) {
+            // r enters ln G as r times the mean fixing time: exact
+            const double tb = tsum * pay.inv_nfix;
+            Xu = X * exp(hr * tb);
+            Xd = X * exp(-hr * tb);
+        } else if (ASIAN) {
             // e^{+-h t_i} summed over the fixings by its Taylor series in h.
             const double a = (double)A, b = (double)B, c = (double)C, d3 = (double)D3;
             const double even = a + 0.5 * hr * hr * c, odd = hr * b + hr * hr * hr / 6.0 * d3;
@@ -494,8 +524,12 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         sc[4] = pay(Dup, Xu);
         sc[5] = pay(Ddn, Xd);
         const double Tu = L.T + L.hT, Td = L.T - L.hT;
-        const double Xt0 = S0 * (ASIAN ? (double)At0 * pay.inv_nfix : exp((double)yt0 * LN2 + L.r * Tu));
-        const double Xt1 = S0 * (ASIAN ? (double)At1 * pay.inv_nfix : exp((double)yt1 * LN2 + L.r * Td));
+        const double Xt0 = S0 * (GEO     ? geo_rel((double)At0, L.tup.dt * L.fix_step_sum)
+                                 : ASIAN ? (double)At0 * pay.inv_nfix
+                                         : exp((double)yt0 * LN2 + L.r * Tu));
+        const double Xt1 = S0 * (GEO     ? geo_rel((double)At1, L.tdn.dt * L.fix_step_sum)
+                                 : ASIAN ? (double)At1 * pay.inv_nfix
+                                         : exp((double)yt1 * LN2 + L.r * Td));
         sc[6] = pay(exp(-L.r * Tu), Xt0);
         sc[7] = pay(exp(-L.r * Td), Xt1);
         est[EST_DELTA] = (sc[0] - sc[1]) / (2.0 * hS);
@@ -711,39 +745,42 @@ __global__ void sobol_shift_kernel(uint64_t seed, const int32_t *perm, uint32_t 
     out[idx] = w.x >> 2;
 }
 
-template <class R, int RNG, bool ASIAN, bool BUMPS, int SCH>
+template <class R, int RNG, int AV, bool BUMPS, int SCH>
 hipError_t launch_t(const PriceLaunch &L, hipStream_t s)
 {
     const dim3 grid(L.blocks_per_rep, L.n_reps);
     const size_t smem = RNG == 1 ? (size_t)L.bridge_depth * 2 * BLOCK * sizeof(R) : 0;
-    hipLaunchKernelGGL((price_kernel<R, RNG, ASIAN, BUMPS, SCH>), grid, dim3(BLOCK), smem, s, L);
+    hipLaunchKernelGGL((price_kernel<R, RNG, AV, BUMPS, SCH>), grid, dim3(BLOCK), smem, s, L);
     return hipGetLastError();
 }
 
-template <class R, int RNG, bool ASIAN, bool BUMPS>
+template <class R, int RNG, int AV, bool BUMPS>
 hipError_t launch_ft(const PriceLaunch &L, hipStream_t s)
 {
     if (L.scheme == 0)
-        return launch_t<R, RNG, ASIAN, BUMPS, 0>(L, s);
+        return launch_t<R, RNG, AV, BUMPS, 0>(L, s);
     if (L.scheme == 1)
-        return launch_t<R, RNG, ASIAN, BUMPS, 1>(L, s);
+        return launch_t<R, RNG, AV, BUMPS, 1>(L, s);
     if (L.scheme == 3)
-        return launch_t<R, RNG, ASIAN, BUMPS, 3>(L, s);
+        return launch_t<R, RNG, AV, BUMPS, 3>(L, s);
     if constexpr (RNG == 0)
-        return launch_t<R, RNG, ASIAN, BUMPS, 2>(L, s);
+        return launch_t<R, RNG, AV, BUMPS, 2>(L, s);
     return hipErrorInvalidValue; // QE draws Philox inputs only (checked by the host)
 }
 
-template <class R, int RNG, bool ASIAN>
+template <class R, int RNG, int AV>
 hipError_t launch_b(const PriceLaunch &L, hipStream_t s)
 {
-    return L.bumps ? launch_ft<R, RNG, ASIAN, true>(L, s) : launch_ft<R, RNG, ASIAN, false>(L, s);
+    return L.bumps ? launch_ft<R, RNG, AV, true>(L, s) : launch_ft<R, RNG, AV, false>(L, s);
 }
 
 template <class R, int RNG> hipError_t launch_a(const PriceLaunch &L, hipStream_t s)
 {
-    const bool asian = L.opt_type == 2 || L.opt_type == 3;
-    return asian ? launch_b<R, RNG, true>(L, s) : launch_b<R, RNG, false>(L, s);
+    if (L.opt_type == 2 || L.opt_type == 3)
+        return launch_b<R, RNG, 1>(L, s);
+    if (L.opt_type == 4 || L.opt_type == 5)
+        return launch_b<R, RNG, 2>(L, s);
+    return launch_b<R, RNG, 0>(L, s);
 }
 
 template <class R> hipError_t launch_r(const PriceLaunch &L, hipStream_t s)

@@ -67,7 +67,8 @@ def test_enum_constants_match_binding():
     import subprocess
     import tempfile
     import paper_2309_10477_amd as hm
-    names = ["HESTON_FP64", "HESTON_FP32", "HESTON_RNG_PHILOX", "HESTON_RNG_SOBOL_BRIDGE",
+    names = ["HESTON_EURO_CALL", "HESTON_EURO_PUT", "HESTON_ASIAN_CALL", "HESTON_ASIAN_PUT",
+             "HESTON_GEO_ASIAN_CALL", "HESTON_GEO_ASIAN_PUT", "HESTON_FP64", "HESTON_FP32", "HESTON_RNG_PHILOX", "HESTON_RNG_SOBOL_BRIDGE",
              "HESTON_FULL_TRUNCATION", "HESTON_ABSORPTION", "HESTON_QE",
              "HESTON_EULER_FULL_TRUNCATION", "HESTON_EULER_ABSORPTION",
              "HESTON_PARTIAL_TRUNCATION", "HESTON_REFLECTION",
@@ -81,7 +82,8 @@ def test_enum_constants_match_binding():
         exe = os.path.join(d, "t")
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         got = [int(v) for v in subprocess.check_output([exe]).split()]
-    want = [hm.FP64, hm.FP32, hm.PHILOX, hm.SOBOL_BRIDGE, hm.FULL_TRUNCATION, hm.ABSORPTION,
+    want = [hm.EURO_CALL, hm.EURO_PUT, hm.ASIAN_CALL, hm.ASIAN_PUT, hm.GEO_ASIAN_CALL,
+            hm.GEO_ASIAN_PUT, hm.FP64, hm.FP32, hm.PHILOX, hm.SOBOL_BRIDGE, hm.FULL_TRUNCATION, hm.ABSORPTION,
             hm.QE, hm.EULER_FULL_TRUNCATION, hm.EULER_ABSORPTION, hm.PARTIAL_TRUNCATION,
             hm.REFLECTION, hm.GREEKS_PATHWISE, hm.GREEKS_BUMP_FUSED, hm.GREEKS_BUMP_PLAIN]
     assert got == want

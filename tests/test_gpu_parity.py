@@ -294,3 +294,74 @@ def test_invalid_arguments_are_rejected(hm, ctx, bad):
     with pytest.raises(hm.HestonError) as e:
         ctx.price_greeks(p, hm.EURO_CALL, n, N, 1, opts)
     assert e.value.status == -1
+
+
+# --- geometric averages -----------------------------------------------------
+
+@pytest.mark.parametrize("opt_type", [4, 5])
+@pytest.mark.parametrize("scheme", [0, 1, 5])
+@pytest.mark.parametrize("fix", [None, (2, 3, 7)], ids=["every-step", "dates"])
+def test_geometric_fp64_ragged(hm, ctx, opt_type, scheme, fix):
+    n, N, seed = 1000 + 37, 7, 0xDEADBEEF12345
+    p = PP if scheme == 1 else PB
+    opts = hm.Options(scheme=scheme, fixings=fix)
+    d = dump(hm, ctx, p, opt_type, n, N, seed, 0, n, opts)
+    check_records(d, p, opt_type, N, seed, 0, n, 0, scheme, fix, True)
+
+
+@pytest.mark.parametrize("opt_type", [4, 5])
+def test_geometric_fp32_daily_fixings(hm, ctx, opt_type):
+    n, N, seed = 4096 + 100, 252, 11
+    d = dump(hm, ctx, PB, opt_type, n, N, seed, 0, n, hm.Options(precision=hm.FP32))
+    check_records(d, PB, opt_type, N, seed, 0, n, 1, 0, None, True)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_geometric_sobol_bridge(hm, ctx, prec):
+    from oracle import sobol
+    R, M, N, seed = 4, 700, 12, 5
+    n = R * M
+    opts = hm.Options(precision=prec, rng=hm.SOBOL_BRIDGE, qmc_replicates=R,
+                      fixings=(3, 6, 9, 12))
+    d = dump(hm, ctx, PB, hm.GEO_ASIAN_CALL, n, N, seed, 0, n, opts)
+    za, zb = sobol.normals(N, 0, n, R, M, seed)
+    check_records(d, PB, oracle.GEO_ASIAN_CALL, N, seed, 0, n, prec, 0, (3, 6, 9, 12), True,
+                  za, zb)
+
+
+def test_geometric_estimates_match_oracle(hm, ctx):
+    n, N, seed = 20_000, 24, 3
+    opts = hm.Options()
+    r = ctx.price_greeks(PB.__dict__, hm.GEO_ASIAN_PUT, n, N, seed, opts)
+    ref = oracle.price_greeks(PB, oracle.GEO_ASIAN_PUT, n, N, seed, threads=8)
+    for k, (v, se) in ref.items():
+        assert r[k][0] == pytest.approx(v, rel=1e-10, abs=1e-12), k
+        assert r[k][1] == pytest.approx(se, rel=1e-6), k
+
+
+def test_geometric_price_against_transform(hm, ctx):
+    """FP32, 2^22 paths, monthly fixings on a daily grid: the Monte-Carlo price
+    sits within 3.5 standard errors, plus the difference to the same dates on a
+    grid twice as fine, of the characteristic-function price of the geometric
+    average."""
+    from oracle import analytic
+    N = 252
+    steps = tuple(range(21, 253, 21))
+    ref = analytic.geometric_asian_call(PB, np.array(steps) / N * PB.T)
+    o1 = hm.Options(precision=hm.FP32, fixings=steps)
+    o2 = hm.Options(precision=hm.FP32, fixings=tuple(2 * s for s in steps))
+    a = ctx.price_greeks(PB.__dict__, hm.GEO_ASIAN_CALL, 1 << 22, N, 17, o1)["price"]
+    b = ctx.price_greeks(PB.__dict__, hm.GEO_ASIAN_CALL, 1 << 22, 2 * N, 17, o2)["price"]
+    assert abs(a[0] - ref) < 3.5 * a[1] + abs(a[0] - b[0])
+
+
+def test_geometric_rejected_by_adjoint_and_batch(hm, ctx):
+    import torch
+    ck = torch.empty(hm.ckpt_bytes(256, 8, 8, hm.FP64), dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(hm.HestonError) as e:
+        ctx.adjoint_forward(PB.__dict__, hm.GEO_ASIAN_CALL, 256, 8, 1, ck, 8, hm.Options())
+    assert e.value.status == -5
+    with pytest.raises(hm.HestonError) as e:
+        ctx.price_batch([dict(params=PB.__dict__, type=hm.GEO_ASIAN_PUT, n_steps=4, n_paths=100,
+                              seed=1, want=1)], hm.Options())
+    assert e.value.status == -5

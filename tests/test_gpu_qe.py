@@ -91,7 +91,7 @@ def check(hm, ctx, p, opt_type, n, N, seed, prec, first=0, bumps=True):
     return d, rec
 
 
-@pytest.mark.parametrize("opt_type", [0, 1, 2, 3])
+@pytest.mark.parametrize("opt_type", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("p", [PB, PF], ids=["feller", "high-vol-of-vol"])
 def test_qe_fp64_parity(hm, ctx, p, opt_type):
     check(hm, ctx, p, opt_type, 1037, 13, 42, 0)
@@ -99,7 +99,7 @@ def test_qe_fp64_parity(hm, ctx, p, opt_type):
 
 @pytest.mark.parametrize("p", [PB, PF], ids=["feller", "high-vol-of-vol"])
 def test_qe_fp32_parity(hm, ctx, p):
-    for t in (0, 2):
+    for t in (0, 2, 4):
         check(hm, ctx, p, t, 4099, 24, 7, 1)
 
 
