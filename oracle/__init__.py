@@ -21,6 +21,7 @@ Contents
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass, astuple
@@ -270,3 +271,66 @@ def price_greeks(p: Params, opt_type: int, n_paths: int, n_steps: int, seed: int
     samples["pw_delta"] = rec[:, 4]
     samples["pw_rho"] = rec[:, 5]
     return {k: tuple(float(v) for v in mean_se(y)) for k, y in samples.items()}
+
+
+# --------------------------------------------------------------------------
+# Geometric-average control variate for the arithmetic Asian (the paper notes
+# that the average may be geometric; using the geometric payoff, whose price
+# has a semi-analytic form, as a control follows Kemna and Vorst, 1990).
+
+def control_variate(a: np.ndarray, g: np.ndarray, mu: float):
+    """Control-variate estimate from per-path arithmetic payoffs a and geometric
+    payoffs g on the same paths, with E[g] = mu known.
+
+    beta = Cov(a, g) / Var(g) (sample moments, n - 1 denominators; 0 when g is
+    constant); estimate = mean(a) - beta (mean(g) - mu); its standard error is
+    sqrt((Var(a) - beta Cov(a, g)) / n), the residual variance of a - beta g.
+    Returns (estimate, std_err, beta)."""
+    a = np.asarray(a, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    n = a.shape[0]
+    ma, mg = a.sum() / n, g.sum() / n
+    va = ((a - ma) ** 2).sum() / (n - 1)
+    vg = ((g - mg) ** 2).sum() / (n - 1)
+    cov = ((a - ma) * (g - mg)).sum() / (n - 1)
+    beta = cov / vg if vg > 0 else 0.0
+    res = max(va - beta * cov, 0.0)
+    return ma - beta * (mg - mu), math.sqrt(res / n), beta
+
+
+def control_variate_reps(a: np.ndarray, g: np.ndarray, mu: float, R: int):
+    """Replicated (quasi-random) form: the paths are R equal replicates in order;
+    beta comes from all paths as in control_variate, each replicate gives
+    mean(a_r) - beta (mean(g_r) - mu), and the estimate and its standard error
+    are the mean of those R values and their std (ddof 1) / sqrt(R)."""
+    _, _, beta = control_variate(a, g, mu)
+    a = np.asarray(a, dtype=np.float64).reshape(R, -1)
+    g = np.asarray(g, dtype=np.float64).reshape(R, -1)
+    e = a.mean(axis=1) - beta * (g.mean(axis=1) - mu)
+    m = e.sum() / R
+    return m, math.sqrt(((e - m) ** 2).sum() / (R - 1) / R), beta
+
+
+def geometric_control_mean(p: Params, opt_type: int, n_steps: int, fixings=None) -> float:
+    """E of the discounted geometric payoff matching an arithmetic Asian type
+    (call for ASIAN_CALL, put for ASIAN_PUT) on the same fixing dates."""
+    from . import analytic
+    steps = np.arange(1, n_steps + 1) if fixings is None else np.asarray(fixings)
+    t = steps / n_steps * p.T
+    if opt_type == ASIAN_CALL:
+        return analytic.geometric_asian_call(p, t)
+    if opt_type == ASIAN_PUT:
+        return analytic.geometric_asian_put(p, t)
+    raise ValueError("the geometric control applies to arithmetic Asian types")
+
+
+def cv_price(p: Params, opt_type: int, n_paths: int, n_steps: int, seed: int,
+             mode: int = FULL_TRUNC, fixings=None, threads: int = 1, first: int = 0):
+    """Arithmetic-Asian price with the geometric control on the same paths.
+    Returns (estimate, std_err, beta, mu, a, g)."""
+    geo = GEO_ASIAN_CALL if opt_type == ASIAN_CALL else GEO_ASIAN_PUT
+    mu = geometric_control_mean(p, opt_type, n_steps, fixings)
+    a = simulate(p, opt_type, n_steps, seed, first, n_paths, mode, fixings, threads=threads)[:, 3]
+    g = simulate(p, geo, n_steps, seed, first, n_paths, mode, fixings, threads=threads)[:, 3]
+    est, se, beta = control_variate(a, g, mu)
+    return est, se, beta, mu, a, g
