@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define HESTON_ABI_VERSION 1
+#define HESTON_ABI_VERSION 2
 
 /* Model and contract inputs (paper: Table "Heston model parameters"). */
 typedef struct heston_params {
@@ -114,12 +114,29 @@ enum {
                                       (exclusive with BUMP_FUSED)                */
 };
 
+/* Control variate of the price (heston_opts.control_variate).  GEOMETRIC
+ * applies to arithmetic-Asian types: on the same paths the kernel also forms
+ * the geometric-average payoff of the same kind and strike on the same fixing
+ * dates (the paper notes that the average may be geometric), whose expectation
+ * the library computes semi-analytically on the device (Heston is affine in
+ * ln S: the transform of ln G follows from closed-form Riccati steps between
+ * fixing dates, the price from Gil-Pelaez inversion by Gauss-Legendre panels).
+ * The estimate is mean(a) - beta (mean(g) - E[g]) with beta = Cov(a, g) /
+ * Var(g) from the same paths (Kemna and Vorst, J. Banking and Finance 14,
+ * 1990); std_err = sqrt((Var(a) - beta Cov(a, g)) / n) (Philox), or the std
+ * of the replicate estimates / sqrt(R) with the pooled beta (Sobol).
+ * Requires sigma > 0 and at most HESTON_CONTROL_MAX_FIXINGS fixing dates;
+ * not with HESTON_GREEKS_BUMP_PLAIN. */
+enum { HESTON_CONTROL_NONE = 0, HESTON_CONTROL_GEOMETRIC = 1 };
+#define HESTON_CONTROL_MAX_FIXINGS 8192
+
 /* valid_mask bits of heston_result. */
 enum {
     HESTON_VALID_PRICE = 1u,
     HESTON_VALID_PATHWISE = 2u,
     HESTON_VALID_BUMPS = 4u,
-    HESTON_VALID_ADJOINT = 8u
+    HESTON_VALID_ADJOINT = 8u,
+    HESTON_VALID_CONTROL = 16u
 };
 
 typedef struct heston_est {
@@ -137,6 +154,9 @@ typedef struct heston_result {
     uint32_t valid_mask;
     uint32_t reserved;
     double device_ms; /* GPU time of the path kernel, HIP events on the context stream */
+    heston_est cv_price; /* price with the control variate (HESTON_VALID_CONTROL)       */
+    double cv_beta;      /* fitted control coefficient beta                             */
+    double cv_mean;      /* E of the discounted control payoff, computed on the device  */
 } heston_result;
 
 typedef struct heston_opts {
@@ -164,6 +184,8 @@ typedef struct heston_opts {
     double bump_r_abs;  /* default 1e-4                               */
     double bump_T_abs;  /* default 1/365; n_steps and the fixing step
                            indices stay fixed, so dt is rescaled      */
+    int32_t control_variate; /* HESTON_CONTROL_NONE (default) or HESTON_CONTROL_GEOMETRIC */
+    uint32_t reserved;       /* must be 0                                               */
 } heston_opts;
 
 typedef struct heston_ctx heston_ctx;

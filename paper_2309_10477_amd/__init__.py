@@ -25,6 +25,10 @@ PHILOX, SOBOL_BRIDGE = 0, 1
 (FULL_TRUNCATION, ABSORPTION, QE, EULER_FULL_TRUNCATION, EULER_ABSORPTION, PARTIAL_TRUNCATION,
  REFLECTION) = 0, 1, 2, 3, 4, 5, 6
 GREEKS_PATHWISE, GREEKS_BUMP_FUSED, GREEKS_BUMP_PLAIN = 1, 2, 4
+ABI_VERSION = 2
+CONTROL_NONE, CONTROL_GEOMETRIC = 0, 1
+CONTROL_MAX_FIXINGS = 8192
+VALID_PRICE, VALID_PATHWISE, VALID_BUMPS, VALID_ADJOINT, VALID_CONTROL = 1, 2, 4, 8, 16
 DUMP_WIDTH = 16
 DUMP_FIELDS = ("S_T", "V_T", "Sbar", "pay", "pw_delta", "pw_rho", "pay_S0+", "pay_S0-",
                "pay_v0+", "pay_v0-", "pay_r+", "pay_r-", "pay_T+", "pay_T-", "x_T", "reserved")
@@ -51,7 +55,8 @@ class CEst(ctypes.Structure):
 class CResult(ctypes.Structure):
     _fields_ = [(n, CEst) for n in EST_NAMES] + [("adj", CEst * 7),
         ("n_paths", ctypes.c_uint64), ("valid_mask", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32), ("device_ms", ctypes.c_double)]
+        ("reserved", ctypes.c_uint32), ("device_ms", ctypes.c_double),
+        ("cv_price", CEst), ("cv_beta", ctypes.c_double), ("cv_mean", ctypes.c_double)]
 
 
 class COpts(ctypes.Structure):
@@ -62,7 +67,8 @@ class COpts(ctypes.Structure):
         ("sobol_directions", ctypes.POINTER(ctypes.c_uint32)), ("sobol_dims", ctypes.c_uint32),
         ("fixing_steps", ctypes.POINTER(ctypes.c_uint32)), ("n_fixings", ctypes.c_uint32),
         ("bump_S0_rel", ctypes.c_double), ("bump_v0_rel", ctypes.c_double),
-        ("bump_r_abs", ctypes.c_double), ("bump_T_abs", ctypes.c_double)]
+        ("bump_r_abs", ctypes.c_double), ("bump_T_abs", ctypes.c_double),
+        ("control_variate", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
 
 
 class CRequest(ctypes.Structure):
@@ -124,6 +130,9 @@ def lib():
     L.heston_last_error.argtypes = []
     L.heston_last_error.restype = c.c_char_p
     L.heston_abi_version.restype = c.c_int
+    if L.heston_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {L.heston_abi_version()}, this binding "
+                          f"expects {ABI_VERSION}; rebuild the library")
     L.heston_bump_revalue.argtypes = [c.c_void_p, P(CParams), c.c_int, c.c_uint64, c.c_uint32,
                                       c.c_uint64, P(COpts), P(CBump), c.c_uint32, P(CEst),
                                       P(CEst), P(CEst), P(c.c_double)]
@@ -176,6 +185,7 @@ class Options:
     bump_v0_rel: float = 0.01
     bump_r_abs: float = 1e-4
     bump_T_abs: float = 1.0 / 365.0
+    control_variate: int = CONTROL_NONE
 
 
 class _OptsHolder:
@@ -188,6 +198,7 @@ class _OptsHolder:
         self.c.greeks, self.c.qmc_replicates = o.greeks, o.qmc_replicates
         self.c.bump_S0_rel, self.c.bump_v0_rel = o.bump_S0_rel, o.bump_v0_rel
         self.c.bump_r_abs, self.c.bump_T_abs = o.bump_r_abs, o.bump_T_abs
+        self.c.control_variate = o.control_variate
         self.fix = self.dirs = None
         if o.fixings is not None:
             self.fix = np.ascontiguousarray(o.fixings, dtype=np.uint32)
@@ -348,6 +359,10 @@ def _result_dict(res: CResult) -> dict:
     out["valid_mask"] = res.valid_mask
     out["n_paths"] = res.n_paths
     out["device_ms"] = res.device_ms
+    if res.valid_mask & VALID_CONTROL:
+        out["cv_price"] = (res.cv_price.value, res.cv_price.std_err)
+        out["cv_beta"] = res.cv_beta
+        out["cv_mean"] = res.cv_mean
     return out
 
 

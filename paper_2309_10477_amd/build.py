@@ -19,7 +19,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ("api.hip", "price_kernel.hip", "adjoint_kernel.hip", "batch_kernel.hip",
-           "batch_api.hip", "server.hip")
+           "batch_api.hip", "server.hip", "geo_control.hip")
 SRC = [os.path.join(HERE, "csrc", f) for f in SOURCES]
 HDRS = [os.path.join(HERE, "csrc", f) for f in ("internal.hpp", "device_math.hpp",
                                                 "path_step.hpp", "runtime.hpp",

@@ -195,6 +195,21 @@ heston_status check_request(const Request &q)
         if (!(o.bump_S0_rel < 1) || !(o.bump_v0_rel < 1) || !(o.bump_T_abs < q.p.T))
             return fail(HESTON_INVALID_ARGUMENT, "bumps must keep S0, v0 and T positive");
     }
+    if (o.reserved != 0)
+        return fail(HESTON_INVALID_ARGUMENT, "opts->reserved must be 0");
+    if (o.control_variate != HESTON_CONTROL_NONE) {
+        if (o.control_variate != HESTON_CONTROL_GEOMETRIC)
+            return fail(HESTON_INVALID_ARGUMENT, "unknown control variate");
+        if (q.type != HESTON_ASIAN_CALL && q.type != HESTON_ASIAN_PUT)
+            return fail(HESTON_INVALID_ARGUMENT,
+                        "the geometric control applies to arithmetic-Asian types");
+        if (!(q.p.sigma > 0))
+            return fail(HESTON_INVALID_ARGUMENT, "the geometric control needs sigma > 0");
+        if ((o.fixing_steps ? o.n_fixings : q.n_steps) > HESTON_CONTROL_MAX_FIXINGS)
+            return fail(HESTON_UNSUPPORTED, "more fixing dates than the geometric control takes");
+        if (o.greeks & HESTON_GREEKS_BUMP_PLAIN)
+            return fail(HESTON_UNSUPPORTED, "the control variate runs with the fused kernel only");
+    }
     const bool asian = q.type >= 2;
     if (asian && o.fixing_steps) {
         if (o.n_fixings < 1)
@@ -241,6 +256,7 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
     L.precision = o.precision;
     L.rng = o.rng;
     L.bumps = (o.greeks & HESTON_GREEKS_BUMP_FUSED) != 0;
+    L.cv = o.control_variate == HESTON_CONTROL_GEOMETRIC;
     L.n_steps = q.n_steps;
     L.seed = q.seed;
     L.first_path = first;
@@ -390,17 +406,18 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
     if ((uint64_t)L.blocks_per_rep * BLOCK < span || L.blocks_per_rep > 0x7FFFFFFFu)
         return fail(HESTON_UNSUPPORTED, "too many paths for one launch");
     heston_status st;
-    if ((st = reserve(c, c->partials, (size_t)L.n_reps * L.blocks_per_rep * N_ACC * 8)) != HESTON_OK ||
-        (st = reserve(c, c->rep_sums, (size_t)L.n_reps * N_ACC * 8)) != HESTON_OK)
+    const size_t W = (size_t)L.acc_width();
+    if ((st = reserve(c, c->partials, (size_t)L.n_reps * L.blocks_per_rep * W * 8)) != HESTON_OK ||
+        (st = reserve(c, c->rep_sums, (size_t)L.n_reps * W * 8)) != HESTON_OK)
         return st;
     L.partials = (double *)c->partials.ptr;
-    if (c->host_sums_bytes < (size_t)L.n_reps * N_ACC * 8) {
+    if (c->host_sums_bytes < (size_t)L.n_reps * W * 8) {
         if (c->host_sums)
             (void)hipHostFree(c->host_sums);
         c->host_sums = nullptr;
         c->host_sums_bytes = 0;
-        HIP_TRY(hipHostMalloc((void **)&c->host_sums, (size_t)L.n_reps * N_ACC * 8));
-        c->host_sums_bytes = (size_t)L.n_reps * N_ACC * 8;
+        HIP_TRY(hipHostMalloc((void **)&c->host_sums, (size_t)L.n_reps * W * 8));
+        c->host_sums_bytes = (size_t)L.n_reps * W * 8;
     }
     return HESTON_OK;
 }
@@ -415,15 +432,15 @@ heston_est est_from(double n, double s, double ss)
 }
 
 // Replicate estimates: mean of the R replicate means, SE = std of them / sqrt(R).
-heston_est est_reps(const double *sums, uint32_t R, double M, int e)
+heston_est est_reps(const double *sums, uint32_t R, double M, int e, int W)
 {
     double mean = 0;
     for (uint32_t r = 0; r < R; ++r)
-        mean += sums[r * N_ACC + 2 * e] / M;
+        mean += sums[r * W + 2 * e] / M;
     mean /= R;
     double ss = 0;
     for (uint32_t r = 0; r < R; ++r) {
-        const double d = sums[r * N_ACC + 2 * e] / M - mean;
+        const double d = sums[r * W + 2 * e] / M - mean;
         ss += d * d;
     }
     return heston_est{mean, R > 1 ? std::sqrt(ss / (R - 1.0) / R) : 0.0};
@@ -560,6 +577,8 @@ heston_status check_adjoint(const Request &q, uint32_t every, const void *ckpt, 
         return fail(HESTON_UNSUPPORTED, "adjoint sensitivities need Philox normals");
     if (q.o.scheme != HESTON_FULL_TRUNCATION && q.o.scheme != HESTON_ABSORPTION)
         return fail(HESTON_UNSUPPORTED, "adjoint sensitivities follow the Milstein scheme");
+    if (q.o.control_variate != HESTON_CONTROL_NONE)
+        return fail(HESTON_UNSUPPORTED, "adjoint calls take no control variate");
     if (q.type > HESTON_ASIAN_PUT)
         return fail(HESTON_UNSUPPORTED, "adjoint sensitivities cover European and arithmetic-Asian payoffs");
     if (!(std::fabs(q.p.rho) < 1))
@@ -632,6 +651,7 @@ heston_status heston_ctx_destroy(heston_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift, &c->sobol_hi, &c->sobol_perm, &c->sobol_dir12,
                       &c->bridge_start, &c->bridge_ops, &c->pay, &c->bump_partials,
+                      &c->geo_buf, &c->geo_partials, &c->geo_steps,
                       &c->bump_sums, &c->step_w, &c->batch_opts, &c->batch_items, &c->batch_partials,
                       &c->batch_sums, &c->batch_counter, &c->batch_scratch})
         if (b->ptr)
@@ -642,6 +662,120 @@ heston_status heston_ctx_destroy(heston_ctx *c)
     (void)hipEventDestroy(c->ev1);
     delete c;
     return HESTON_OK;
+}
+
+// Positive nodes and weights of the 16-point Gauss-Legendre rule: Newton's
+// method on the three-term recurrence of the Legendre polynomials, from the
+// usual cosine first guesses; w = 2 / ((1 - x^2) P16'(x)^2).
+static void gauss_legendre16(double x[8], double w[8])
+{
+    constexpr int n = 16;
+    for (int i = 0; i < n / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            double p = 1.0, pm = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                const double pk = ((2.0 * k - 1.0) * z * p - (k - 1.0) * pm) / k;
+                pm = p;
+                p = pk;
+            }
+            dp = n * (z * p - pm) / (z * z - 1.0);
+            const double dz = p / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16)
+                break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Inputs of the geometric control's device price: model, fixing dates (copied
+// to the device when given explicitly), quadrature rule, buffers.
+static heston_status geo_control_setup(heston_ctx *c, const Request &q, GeoControl &g)
+{
+    const heston_params &p = q.p;
+    const heston_opts &o = q.o;
+    std::memset(&g, 0, sizeof(g));
+    g.lnS0 = std::log(p.S0);
+    g.K = p.K;
+    g.lnK = std::log(p.K);
+    g.r = p.r;
+    g.T = p.T;
+    g.v0 = p.v0;
+    g.kappa = p.kappa;
+    g.theta = p.theta;
+    g.sigma = p.sigma;
+    g.rho = p.rho;
+    g.dt = p.T / q.n_steps;
+    g.n_fix = o.fixing_steps ? o.n_fixings : q.n_steps;
+    heston_status st;
+    if (o.fixing_steps) {
+        if ((st = reserve(c, c->geo_steps, (size_t)o.n_fixings * 4)) != HESTON_OK)
+            return st;
+        HIP_TRY(hipMemcpyAsync(c->geo_steps.ptr, o.fixing_steps, (size_t)o.n_fixings * 4,
+                               hipMemcpyHostToDevice, c->stream));
+        g.steps = (const uint32_t *)c->geo_steps.ptr;
+    }
+    static const struct Rule {
+        double x[8], w[8];
+        Rule() { gauss_legendre16(x, w); }
+    } rule;
+    std::memcpy(g.gl_x, rule.x, sizeof(g.gl_x));
+    std::memcpy(g.gl_w, rule.w, sizeof(g.gl_w));
+    if ((st = reserve(c, c->geo_buf, GEO_BUF_DOUBLES * 8)) != HESTON_OK ||
+        (st = reserve(c, c->geo_partials, (size_t)geo_node_blocks() * 8)) != HESTON_OK)
+        return st;
+    return HESTON_OK;
+}
+
+// Control-variate estimate from the replicate sums of a (arithmetic payoff),
+// g (geometric payoff) and a - g: beta = Cov(a, g) / Var(g) over all paths,
+// with Cov(a, g) = (Var(a) + Var(g) - Var(a - g)) / 2.
+static void cv_combine(const double *s, const PriceLaunch &L, bool reps, uint64_t n_paths,
+                       double mu, heston_result &r)
+{
+    const int W = N_ACC_CV;
+    double Sa = 0, Saa = 0, Sg = 0, Sgg = 0, Sd = 0, Sdd = 0;
+    for (uint32_t k = 0; k < L.n_reps; ++k) {
+        const double *x = s + (size_t)k * W;
+        Sa += x[2 * EST_PRICE];
+        Saa += x[2 * EST_PRICE + 1];
+        Sg += x[2 * EST_CV_GEO];
+        Sgg += x[2 * EST_CV_GEO + 1];
+        Sd += x[2 * EST_CV_DIFF];
+        Sdd += x[2 * EST_CV_DIFF + 1];
+    }
+    const double n = (double)n_paths;
+    auto var = [n](double S, double SS) { return (SS - S * (S / n)) / (n - 1.0); };
+    const double va = var(Sa, Saa), vg = var(Sg, Sgg), vd = var(Sd, Sdd);
+    const double cov = 0.5 * (va + vg - vd);
+    const double beta = vg > 0 ? cov / vg : 0.0;
+    heston_est e;
+    if (!reps) {
+        e.value = Sa / n - beta * (Sg / n - mu);
+        e.std_err = std::sqrt(std::max(va - beta * cov, 0.0) / n);
+    } else {
+        const double M = (double)L.paths_per_rep;
+        const uint32_t R = L.n_reps;
+        double m = 0;
+        for (uint32_t k = 0; k < R; ++k)
+            m += s[(size_t)k * W + 2 * EST_PRICE] / M -
+                 beta * (s[(size_t)k * W + 2 * EST_CV_GEO] / M - mu);
+        m /= R;
+        double ss = 0;
+        for (uint32_t k = 0; k < R; ++k) {
+            const double d = s[(size_t)k * W + 2 * EST_PRICE] / M -
+                             beta * (s[(size_t)k * W + 2 * EST_CV_GEO] / M - mu) - m;
+            ss += d * d;
+        }
+        e.value = m;
+        e.std_err = R > 1 ? std::sqrt(ss / (R - 1.0) / R) : 0.0;
+    }
+    r.cv_price = e;
+    r.cv_beta = beta;
+    r.cv_mean = mu;
+    r.valid_mask |= HESTON_VALID_CONTROL;
 }
 
 heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
@@ -687,11 +821,22 @@ heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
     if ((st = plan(c, q, 0, n_paths, L)) != HESTON_OK)
         return st;
     L.dump = nullptr;
+    GeoControl gc;
+    if (L.cv && (st = geo_control_setup(c, q, gc)) != HESTON_OK)
+        return st;
     HIP_TRY(hipEventRecord(c->ev0, c->stream));
     HIP_TRY(launch_paths(L, c->stream));
     HIP_TRY(hipEventRecord(c->ev1, c->stream));
     HIP_TRY(launch_reduce(L, (double *)c->rep_sums.ptr, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->host_sums, c->rep_sums.ptr, (size_t)L.n_reps * N_ACC * 8,
+    double geo_out[4] = {0, 0, 0, 0};
+    if (L.cv) {
+        double *buf = (double *)c->geo_buf.ptr;
+        HIP_TRY(launch_geo_bound(gc, buf, c->stream));
+        HIP_TRY(launch_geo_price(gc, (double *)c->geo_partials.ptr, buf, c->stream));
+        HIP_TRY(hipMemcpyAsync(geo_out, buf + GEO_OUT, sizeof(geo_out), hipMemcpyDeviceToHost,
+                               c->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(c->host_sums, c->rep_sums.ptr, (size_t)L.n_reps * L.acc_width() * 8,
                            hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     float ms = 0;
@@ -705,11 +850,18 @@ heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
     const int n_est = L.bumps ? N_EST : EST_DELTA;
     for (int e = 0; e < n_est; ++e)
         *slot[e] = q.o.rng == HESTON_RNG_SOBOL_BRIDGE
-                       ? est_reps(s, L.n_reps, (double)L.paths_per_rep, e)
+                       ? est_reps(s, L.n_reps, (double)L.paths_per_rep, e, L.acc_width())
                        : est_from((double)n_paths, s[2 * e], s[2 * e + 1]);
     r.n_paths = n_paths;
     r.valid_mask = HESTON_VALID_PRICE | HESTON_VALID_PATHWISE | (L.bumps ? HESTON_VALID_BUMPS : 0u);
     r.device_ms = ms;
+    if (L.cv) {
+        const double mu = q.type == HESTON_ASIAN_CALL ? geo_out[0] : geo_out[1];
+        if (!std::isfinite(mu))
+            return fail(HESTON_UNSUPPORTED,
+                        "the geometric control's transform has not decayed by v = 2^14");
+        cv_combine(s, L, q.o.rng == HESTON_RNG_SOBOL_BRIDGE, n_paths, mu, r);
+    }
     *out = r;
     return HESTON_OK;
 }
@@ -770,6 +922,8 @@ heston_status heston_bump_revalue(heston_ctx *c, const heston_params *params,
     heston_status st = check_request(q);
     if (st != HESTON_OK)
         return st;
+    if (q.o.control_variate != HESTON_CONTROL_NONE)
+        return fail(HESTON_UNSUPPORTED, "bump-and-revalue takes no control variate");
     DeviceGuard g(c->device);
     return bump_revalue_impl(c, q, bumps, n_bumps, price, first, second, device_ms, nullptr);
 }

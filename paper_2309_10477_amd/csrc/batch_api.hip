@@ -214,6 +214,8 @@ extern "C" heston_status heston_price_batch(heston_ctx *c, const heston_request 
         return fail(HESTON_UNSUPPORTED, "batches use the Milstein scheme");
     if (o.fixing_steps)
         return fail(HESTON_INVALID_ARGUMENT, "batched Asians fix at every step; fixing_steps must be NULL");
+    if (o.control_variate != HESTON_CONTROL_NONE)
+        return fail(HESTON_UNSUPPORTED, "batches take no control variate");
     std::vector<heston_request> rq(reqs, reqs + n);
     std::vector<uint64_t> begin(n, 0), count(n);
     uint64_t total = 0;

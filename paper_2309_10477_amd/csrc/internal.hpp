@@ -20,6 +20,10 @@ enum Estimator : int {
     N_EST
 };
 constexpr int N_ACC = 2 * N_EST;   // doubles per partial record
+// The arithmetic-Asian kernel with the geometric control adds two estimators:
+// the geometric payoff g and the difference a - g of the two payoffs.
+enum : int { EST_CV_GEO = N_EST, EST_CV_DIFF, N_EST_CV };
+constexpr int N_ACC_CV = 2 * N_EST_CV;
 constexpr int DUMP_WIDTH = 16;
 constexpr int BLOCK = 256;         // threads per block of the path kernels
 constexpr int MAX_BRIDGE_DEPTH = 24;
@@ -55,6 +59,7 @@ struct PriceLaunch {
     int precision;     // 0 fp64, 1 fp32
     int rng;           // 0 Philox, 1 Sobol + bridge
     bool bumps;        // fused bump scenarios
+    bool cv;           // arithmetic Asian with the geometric control (records N_ACC_CV wide)
     uint32_t n_steps;
     uint32_t n_fix;                 // number of fixing dates
     double fix_step_sum;            // sum of the fixing step indices (fixing times / dt)
@@ -83,13 +88,26 @@ struct PriceLaunch {
     double bridge_root_scale;       // sqrt(N)
     int bridge_depth;
     // outputs
-    double *partials;               // device [n_reps][blocks_per_rep][N_ACC]
+    double *partials;               // device [n_reps][blocks_per_rep][acc_width()]
     uint32_t blocks_per_rep;
     double *dump;                   // device [n_paths][DUMP_WIDTH] or null
     double *pay_out;                // device [n_paths] discounted payoff per path, or null
     const void *step_weights;       // device [N][STEP_WEIGHTS] in the path precision (Asian)
     void *ckpt;                     // device checkpoint buffer (adjoint forward) or null
     uint32_t ckpt_every;            // steps between checkpoints
+
+    // doubles per partial record
+    __host__ __device__ int acc_width() const { return cv ? N_ACC_CV : N_ACC; }
+};
+
+// Semi-analytic price of the geometric-average control (geo_control.hip).
+struct GeoControl {
+    double lnS0, K, lnK, r, T, v0, kappa, theta, sigma, rho;
+    double dt;                 // fixing time of step k is k dt
+    const uint32_t *steps;     // fixing steps (device), or null = every step 1..n_fix
+    uint32_t n_fix;
+    uint32_t n_panels;         // Gauss-Legendre panels of unit width on [0, n_panels]
+    double gl_x[8], gl_w[8];   // positive 16-point Gauss-Legendre nodes and weights
 };
 
 // Wave-uniform constants of one option's paths (single scenario).
@@ -182,8 +200,22 @@ hipError_t launch_reduce_rows(const double *partials, uint32_t rows, uint32_t w,
 // Launches the path kernel of `L` on `stream` (one partial record per block).
 hipError_t launch_paths(const PriceLaunch &L, hipStream_t stream);
 // Sums the partial records of each replicate, in a fixed order, into
-// `rep_sums` (device [n_reps][N_ACC]).
+// `rep_sums` (device [n_reps][L.acc_width()]).
 hipError_t launch_reduce(const PriceLaunch &L, double *rep_sums, hipStream_t stream);
+
+// Geometric-average control, in one device buffer `buf` of GEO_BUF_DOUBLES:
+// [0, 2 GEO_BOUND_POINTS) the modulus bounds |M(1 + iv)| / v and K |M(iv)| / v
+// at v = 2^k (M the transform of ln G), then at GEO_OUT the discounted call
+// and put prices of G, E[G] and the Gil-Pelaez integral (prices NaN when the
+// transform has not decayed by v = 2^14).  `partials` (device
+// [geo_node_blocks()]) holds one double per block of the node kernel.
+constexpr int GEO_BOUND_POINTS = 15;
+constexpr int GEO_OUT = 2 * GEO_BOUND_POINTS;
+constexpr int GEO_BUF_DOUBLES = GEO_OUT + 4;
+hipError_t launch_geo_bound(const GeoControl &g, double *buf, hipStream_t stream);
+uint32_t geo_node_blocks();
+hipError_t launch_geo_price(const GeoControl &g, double *partials, double *buf,
+                            hipStream_t stream);
 
 // Fills the [N][STEP_WEIGHTS] fixing weights of `L` (its precision) at
 // L.step_weights.

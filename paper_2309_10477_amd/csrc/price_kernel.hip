@@ -220,13 +220,15 @@ __device__ __forceinline__ void qe_step(R &y, R &w, const QEGrid<R> &g, R z1l, R
 template <class R, int RNG, int AV, bool BUMPS, int SCH>
 __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
 {
-    // AV: 0 European, 1 arithmetic average, 2 geometric average over the fixings.
+    // AV: 0 European, 1 arithmetic average, 2 geometric average over the
+    // fixings, 3 arithmetic average with the geometric one as its control.
     // SCH: 0 Milstein with full truncation, 1 Milstein with absorption, 2 QE,
     // 3 Milstein with partial truncation or reflection (L.reflect)
-    constexpr bool ASIAN = AV != 0, GEO = AV == 2;
+    constexpr bool ASIAN = AV != 0, GEO = AV == 2, CV = AV == 3;
+    constexpr int NE = CV ? N_EST_CV : N_EST, NA = 2 * NE;
     constexpr bool FT = SCH == 0;
     extern __shared__ unsigned char smem_raw[];
-    __shared__ double red[BLOCK / 64][N_ACC];
+    __shared__ double red[BLOCK / 64][NA];
 
     const uint32_t rep = L.rep0 + blockIdx.y;
     const uint64_t M = L.paths_per_rep;
@@ -247,6 +249,7 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
     R yv0 = 0, yv1 = 0, wv0 = (R)((L.v0 + L.hv) * L.base.dt), wv1 = (R)((L.v0 - L.hv) * L.base.dt);
     R yt0 = 0, yt1 = 0, wt0 = (R)(L.v0 * L.tup.dt), wt1 = (R)(L.v0 * L.tdn.dt);
     R Av0 = 0, Av1 = 0, At0 = 0, At1 = 0;
+    R Gs = 0; // control: sum of y over the fixings (base scenario)
     if constexpr (BUMPS) {
         gu = grid<R>(L.tup, L.sigma);
         gd = grid<R>(L.tdn, L.sigma);
@@ -280,6 +283,8 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
                 const R e = exp2r(y);
                 A += tw[0] * e;
                 B += tw[1] * e;
+                if constexpr (CV)
+                    Gs += y;
                 if constexpr (BUMPS) {
                     C += tw[2] * e;
                     if constexpr (sizeof(R) == 8)
@@ -466,7 +471,7 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
     }
 
     // ---- payoffs and Greek samples, in FP64 ----
-    double est[N_EST];
+    double est[NE];
     const Payoff pay{L.opt_type, L.K, 1.0 / (double)L.n_fix};
     const double S0 = L.S0, D = exp(-L.r * L.T);
     const double x = (double)y * LN2 + L.r * L.T;
@@ -543,6 +548,13 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
             est[e] = 0.0;
     }
 
+    double gpay = 0.0; // control payoff
+    if constexpr (CV) {
+        gpay = pay(D, S0 * geo_rel((double)Gs, tsum));
+        est[EST_CV_GEO] = gpay;
+        est[EST_CV_DIFF] = est[EST_PRICE] - gpay;
+    }
+
     if (L.pay_out != nullptr && active)
         L.pay_out[p - L.first_path] = est[EST_PRICE];
 
@@ -559,13 +571,13 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         for (int k = 0; k < 8; ++k)
             rec[6 + k] = BUMPS ? sc[k] : nan;
         rec[14] = x;
-        rec[15] = 0.0;
+        rec[15] = gpay;
     }
 
     // ---- FP64 sums: wavefront butterfly, then the block's waves in order ----
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int e = 0; e < N_EST; ++e) {
+    for (int e = 0; e < NE; ++e) {
         const double ye = active ? est[e] : 0.0;
         const double s1 = wave_sum(ye);
         const double s2 = wave_sum(ye * ye);
@@ -575,43 +587,44 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         }
     }
     __syncthreads();
-    if (threadIdx.x < N_ACC) {
+    if (threadIdx.x < NA) {
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < BLOCK / 64; ++w)
             s += red[w][threadIdx.x];
-        L.partials[((uint64_t)blockIdx.y * L.blocks_per_rep + blockIdx.x) * N_ACC + threadIdx.x] = s;
+        L.partials[((uint64_t)blockIdx.y * L.blocks_per_rep + blockIdx.x) * NA + threadIdx.x] = s;
     }
 }
 
-// Sums the partial records of each replicate in a fixed order.
+// Sums the partial records (W doubles each) of each replicate in a fixed order.
+template <int W>
 __global__ __launch_bounds__(BLOCK) void reduce_partials(const double *__restrict__ partials,
                                                          uint32_t blocks_per_rep,
                                                          double *__restrict__ rep_sums)
 {
-    __shared__ double red[BLOCK][N_ACC + 1];
-    const double *base = partials + (uint64_t)blockIdx.x * blocks_per_rep * N_ACC;
-    double acc[N_ACC];
+    __shared__ double red[BLOCK][W + 1];
+    const double *base = partials + (uint64_t)blockIdx.x * blocks_per_rep * W;
+    double acc[W];
 #pragma unroll
-    for (int k = 0; k < N_ACC; ++k)
+    for (int k = 0; k < W; ++k)
         acc[k] = 0.0;
     for (uint32_t b = threadIdx.x; b < blocks_per_rep; b += BLOCK)
 #pragma unroll
-        for (int k = 0; k < N_ACC; ++k)
-            acc[k] += base[(uint64_t)b * N_ACC + k];
+        for (int k = 0; k < W; ++k)
+            acc[k] += base[(uint64_t)b * W + k];
 #pragma unroll
-    for (int k = 0; k < N_ACC; ++k)
+    for (int k = 0; k < W; ++k)
         red[threadIdx.x][k] = acc[k];
     __syncthreads();
     for (int s = BLOCK / 2; s > 0; s >>= 1) {
         if (threadIdx.x < (unsigned)s)
 #pragma unroll
-            for (int k = 0; k < N_ACC; ++k)
+            for (int k = 0; k < W; ++k)
                 red[threadIdx.x][k] += red[threadIdx.x + s][k];
         __syncthreads();
     }
-    if (threadIdx.x < N_ACC)
-        rep_sums[(uint64_t)blockIdx.x * N_ACC + threadIdx.x] = red[0][threadIdx.x];
+    if (threadIdx.x < W)
+        rep_sums[(uint64_t)blockIdx.x * W + threadIdx.x] = red[0][threadIdx.x];
 }
 
 // Plain bump-and-revalue: per-path central differences of stored payoff rows.
@@ -777,7 +790,7 @@ hipError_t launch_b(const PriceLaunch &L, hipStream_t s)
 template <class R, int RNG> hipError_t launch_a(const PriceLaunch &L, hipStream_t s)
 {
     if (L.opt_type == 2 || L.opt_type == 3)
-        return launch_b<R, RNG, 1>(L, s);
+        return L.cv ? launch_b<R, RNG, 3>(L, s) : launch_b<R, RNG, 1>(L, s);
     if (L.opt_type == 4 || L.opt_type == 5)
         return launch_b<R, RNG, 2>(L, s);
     return launch_b<R, RNG, 0>(L, s);
@@ -845,8 +858,12 @@ hipError_t launch_reduce_rows(const double *partials, uint32_t rows, uint32_t w,
 
 hipError_t launch_reduce(const PriceLaunch &L, double *rep_sums, hipStream_t stream)
 {
-    hipLaunchKernelGGL(reduce_partials, dim3(L.n_reps), dim3(BLOCK), 0, stream, L.partials,
-                       L.blocks_per_rep, rep_sums);
+    if (L.cv)
+        hipLaunchKernelGGL(reduce_partials<N_ACC_CV>, dim3(L.n_reps), dim3(BLOCK), 0, stream,
+                           L.partials, L.blocks_per_rep, rep_sums);
+    else
+        hipLaunchKernelGGL(reduce_partials<N_ACC>, dim3(L.n_reps), dim3(BLOCK), 0, stream,
+                           L.partials, L.blocks_per_rep, rep_sums);
     return hipGetLastError();
 }
 

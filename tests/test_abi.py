@@ -32,7 +32,8 @@ def test_every_declared_function_is_exported(L):
 
 def test_host_only_calls(L):
     import paper_2309_10477_amd as hm
-    assert L.heston_abi_version() == 1
+    import paper_2309_10477_amd as hm
+    assert L.heston_abi_version() == hm.ABI_VERSION
     assert L.heston_status_str(-1) == b"invalid argument"
     o = hm.COpts()
     assert L.heston_default_opts(ctypes.byref(o)) == 0
@@ -48,9 +49,11 @@ def test_struct_layout_matches_header():
     import tempfile
     import paper_2309_10477_amd as hm
     src = ('#include "heston.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){'
-           'printf("%zu %zu %zu %zu %zu\\n", sizeof(heston_params), sizeof(heston_opts),'
-           ' sizeof(heston_result), offsetof(heston_opts, fixing_steps),'
-           ' offsetof(heston_result, device_ms)); return 0;}\n')
+           'printf("%zu %zu %zu %zu %zu %zu %zu %d %d %d\\n", sizeof(heston_params),'
+           ' sizeof(heston_opts), sizeof(heston_result), offsetof(heston_opts, fixing_steps),'
+           ' offsetof(heston_result, device_ms), offsetof(heston_opts, control_variate),'
+           ' offsetof(heston_result, cv_mean), HESTON_CONTROL_GEOMETRIC, HESTON_VALID_CONTROL,'
+           ' HESTON_CONTROL_MAX_FIXINGS); return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         open(c, "w").write(src)
@@ -58,7 +61,9 @@ def test_struct_layout_matches_header():
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     want = [ctypes.sizeof(hm.CParams), ctypes.sizeof(hm.COpts), ctypes.sizeof(hm.CResult),
-            hm.COpts.fixing_steps.offset, hm.CResult.device_ms.offset]
+            hm.COpts.fixing_steps.offset, hm.CResult.device_ms.offset,
+            hm.COpts.control_variate.offset, hm.CResult.cv_mean.offset, hm.CONTROL_GEOMETRIC,
+            hm.VALID_CONTROL, hm.CONTROL_MAX_FIXINGS]
     assert got == want
 
 
@@ -67,7 +72,7 @@ def test_enum_constants_match_binding():
     import subprocess
     import tempfile
     import paper_2309_10477_amd as hm
-    names = ["HESTON_EURO_CALL", "HESTON_EURO_PUT", "HESTON_ASIAN_CALL", "HESTON_ASIAN_PUT",
+    names = ["HESTON_ABI_VERSION", "HESTON_EURO_CALL", "HESTON_EURO_PUT", "HESTON_ASIAN_CALL", "HESTON_ASIAN_PUT",
              "HESTON_GEO_ASIAN_CALL", "HESTON_GEO_ASIAN_PUT", "HESTON_FP64", "HESTON_FP32", "HESTON_RNG_PHILOX", "HESTON_RNG_SOBOL_BRIDGE",
              "HESTON_FULL_TRUNCATION", "HESTON_ABSORPTION", "HESTON_QE",
              "HESTON_EULER_FULL_TRUNCATION", "HESTON_EULER_ABSORPTION",
@@ -82,7 +87,7 @@ def test_enum_constants_match_binding():
         exe = os.path.join(d, "t")
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         got = [int(v) for v in subprocess.check_output([exe]).split()]
-    want = [hm.EURO_CALL, hm.EURO_PUT, hm.ASIAN_CALL, hm.ASIAN_PUT, hm.GEO_ASIAN_CALL,
+    want = [hm.ABI_VERSION, hm.EURO_CALL, hm.EURO_PUT, hm.ASIAN_CALL, hm.ASIAN_PUT, hm.GEO_ASIAN_CALL,
             hm.GEO_ASIAN_PUT, hm.FP64, hm.FP32, hm.PHILOX, hm.SOBOL_BRIDGE, hm.FULL_TRUNCATION, hm.ABSORPTION,
             hm.QE, hm.EULER_FULL_TRUNCATION, hm.EULER_ABSORPTION, hm.PARTIAL_TRUNCATION,
             hm.REFLECTION, hm.GREEKS_PATHWISE, hm.GREEKS_BUMP_FUSED, hm.GREEKS_BUMP_PLAIN]
