@@ -10,7 +10,9 @@ parameters only (nothing to stage); the timed region covers the library call.
 Prints ONE JSON line (rank 0).  Also reported: the roofline of the path kernel
 (an operation count per path-step against the FP32 vector peak), the Sobol +
 Brownian-bridge variant of the same step, the same step under the
-quadratic-exponential scheme, the adjoint against plain bump-and-revalue, the 4096-option batch, the serving loop's latency, and the
+quadratic-exponential scheme, the same step with the geometric-average control
+variate, the adjoint against plain bump-and-revalue, the 4096-option batch,
+the serving loop's latency, and the
 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -58,8 +60,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="qmc,qe,adjoint,batch,serve",
-                    help="extra legs reported after the timed steps: qmc, qe, adjoint, batch, serve, "
+    ap.add_argument("--legs", default="qmc,qe,cv,adjoint,batch,serve",
+                    help="extra legs reported after the timed steps: qmc, qe, cv, adjoint, batch, serve, "
                          "and copy (a 256 MiB device copy that calibrates HBM byte counters)")
     return ap.parse_args()
 
@@ -305,6 +307,26 @@ def main():
         out["qe_scheme"] = {"value": path_steps / (e_ms * 1e-3), "unit": "path-steps/s",
                             "ms_per_step": e_ms, "kernel_ms": float(np.mean(ek)),
                             "price": re_["price"]}
+    if "cv" in legs:
+        # the same step with the geometric-average control variate on the price:
+        # wall time includes the control's device-side transform price
+        copts = hm.Options(precision=hm.FP32, control_variate=hm.CONTROL_GEOMETRIC)
+        for _ in range(2):
+            ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, copts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ck = []
+        for _ in range(5):
+            rc = ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, copts)
+            ck.append(rc["device_ms"])
+        torch.cuda.synchronize()
+        c_ms = (time.perf_counter() - t1) / 5 * 1e3
+        vrf = (rc["price"][1] / rc["cv_price"][1]) ** 2
+        out["geometric_control_variate"] = {
+            "value": path_steps / (c_ms * 1e-3), "unit": "path-steps/s", "ms_per_step": c_ms,
+            "kernel_ms": float(np.mean(ck)), "price": rc["price"], "cv_price": rc["cv_price"],
+            "cv_beta": rc["cv_beta"], "cv_mean": rc["cv_mean"], "variance_reduction": vrf,
+            "equal_se_path_steps_per_s": path_steps / (c_ms * 1e-3) * vrf}
     if "adjoint" in legs:
         out["adjoint_vs_bump"] = adjoint_vs_bump(ctx, hm, torch)
     if "batch" in legs:

@@ -660,6 +660,12 @@ heston_status heston_ctx_destroy(heston_ctx *c)
         (void)hipHostFree(c->host_sums);
     (void)hipEventDestroy(c->ev0);
     (void)hipEventDestroy(c->ev1);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+        (void)hipEventDestroy(c->fork);
+        (void)hipEventDestroy(c->join);
+    }
     delete c;
     return HESTON_OK;
 }
@@ -717,6 +723,27 @@ static heston_status geo_control_setup(heston_ctx *c, const Request &q, GeoContr
                                hipMemcpyHostToDevice, c->stream));
         g.steps = (const uint32_t *)c->geo_steps.ptr;
     }
+    // First integration range: where a normal ln G with the variance of the
+    // average of a Brownian motion of variance rate min(v0, theta) (the slower
+    // decay of the two levels) has decayed, exp(-v^2 s^2 / 2) = e^-39, times 3
+    // for the heavier tails of the Heston transform; a power of two in [64,
+    // GEO_MAX_FIXED_PANELS].  If the transform has not decayed there, the
+    // device search takes over.
+    {
+        const uint32_t n = g.n_fix;
+        double mm = 0; // sum over i, j of min(t_i, t_j), times in increasing order
+        for (uint32_t k = 0; k < n; ++k)
+            mm += (o.fixing_steps ? (double)o.fixing_steps[k] : (double)(k + 1)) * g.dt *
+                  (2.0 * (n - k) - 1.0);
+        const double vmin = std::min(p.v0, p.theta) > 0 ? std::min(p.v0, p.theta)
+                                                        : std::max(p.v0, p.theta);
+        const double s2 = vmin * mm / ((double)n * n);
+        const double v = s2 > 0 ? 3.0 * std::sqrt(78.0 / s2) : 1e300;
+        uint32_t panels = 64;
+        while (panels < GEO_MAX_FIXED_PANELS && panels < v)
+            panels *= 2;
+        g.n_panels = panels;
+    }
     static const struct Rule {
         double x[8], w[8];
         Rule() { gauss_legendre16(x, w); }
@@ -726,6 +753,11 @@ static heston_status geo_control_setup(heston_ctx *c, const Request &q, GeoContr
     if ((st = reserve(c, c->geo_buf, GEO_BUF_DOUBLES * 8)) != HESTON_OK ||
         (st = reserve(c, c->geo_partials, (size_t)geo_node_blocks() * 8)) != HESTON_OK)
         return st;
+    if (!c->side) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
+    }
     return HESTON_OK;
 }
 
@@ -822,23 +854,38 @@ heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
         return st;
     L.dump = nullptr;
     GeoControl gc;
-    if (L.cv && (st = geo_control_setup(c, q, gc)) != HESTON_OK)
-        return st;
+    if (L.cv) {
+        // the control's price (latency-bound, few waves) runs on the side
+        // stream while the path kernel fills the device
+        if ((st = geo_control_setup(c, q, gc)) != HESTON_OK)
+            return st;
+        HIP_TRY(hipEventRecord(c->fork, c->stream));
+        HIP_TRY(hipStreamWaitEvent(c->side, c->fork, 0));
+        HIP_TRY(launch_geo_price_fixed(gc, (double *)c->geo_partials.ptr,
+                                       (double *)c->geo_buf.ptr, c->side));
+        HIP_TRY(hipEventRecord(c->join, c->side));
+    }
     HIP_TRY(hipEventRecord(c->ev0, c->stream));
     HIP_TRY(launch_paths(L, c->stream));
     HIP_TRY(hipEventRecord(c->ev1, c->stream));
     HIP_TRY(launch_reduce(L, (double *)c->rep_sums.ptr, c->stream));
-    double geo_out[4] = {0, 0, 0, 0};
+    double geo_out[2] = {0, 0};
     if (L.cv) {
-        double *buf = (double *)c->geo_buf.ptr;
-        HIP_TRY(launch_geo_bound(gc, buf, c->stream));
-        HIP_TRY(launch_geo_price(gc, (double *)c->geo_partials.ptr, buf, c->stream));
-        HIP_TRY(hipMemcpyAsync(geo_out, buf + GEO_OUT, sizeof(geo_out), hipMemcpyDeviceToHost,
-                               c->stream));
+        HIP_TRY(hipStreamWaitEvent(c->stream, c->join, 0));
+        HIP_TRY(hipMemcpyAsync(geo_out, (double *)c->geo_buf.ptr + GEO_OUT, sizeof(geo_out),
+                               hipMemcpyDeviceToHost, c->stream));
     }
     HIP_TRY(hipMemcpyAsync(c->host_sums, c->rep_sums.ptr, (size_t)L.n_reps * L.acc_width() * 8,
                            hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    if (L.cv && !(std::isfinite(geo_out[0]) && std::isfinite(geo_out[1]))) {
+        // the transform had not decayed by the end of the fixed range: search
+        HIP_TRY(launch_geo_price_search(gc, (double *)c->geo_partials.ptr,
+                                        (double *)c->geo_buf.ptr, c->stream));
+        HIP_TRY(hipMemcpyAsync(geo_out, (double *)c->geo_buf.ptr + GEO_OUT, sizeof(geo_out),
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
 

@@ -16,11 +16,14 @@
 // Gauss-Legendre on unit panels up to the first power of two where the
 // integrand's modulus bound falls below 1e-15 (E[G] + K).
 //
-// Three launches, no host synchronisation: the bound kernel (one wave)
-// evaluates the bound at v = 2^k and E[G]; the node kernel (a fixed grid whose
-// blocks beyond the chosen panel count only write a zero partial) evaluates
-// one transform per thread; the finish kernel sums the block partials in a
-// fixed order.
+// Each thread evaluates one transform (a sequential pass over the fixing
+// dates), so a launch is bound by that chain's latency, not by throughput.
+// The first pass integrates over [0, g.n_panels] (a range the host sizes from
+// the variance of ln G) in one node launch that also evaluates the bound at
+// its end; only if that bound is not small does the caller run the search: a bound kernel (one wave) at v =
+// 2^k, then nodes up to the first 2^k whose bound is small (a fixed grid whose
+// blocks beyond it only write a zero partial).  A finish kernel sums the block
+// partials in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -48,15 +51,16 @@ __device__ __forceinline__ Cx operator*(Cx a, Cx b)
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 __device__ __forceinline__ Cx operator*(Cx a, double s) { return {a.re * s, a.im * s}; }
-// Smith's division (no overflow of |b|^2 for large operands).
+// Smith's division (no overflow of |b|^2 for large operands), two real
+// divisions.
 __device__ __forceinline__ Cx operator/(Cx a, Cx b)
 {
     if (fabs(b.re) >= fabs(b.im)) {
-        const double t = b.im / b.re, den = b.re + b.im * t;
-        return {(a.re + a.im * t) / den, (a.im - a.re * t) / den};
+        const double t = b.im / b.re, inv = 1.0 / (b.re + b.im * t);
+        return {(a.re + a.im * t) * inv, (a.im - a.re * t) * inv};
     }
-    const double t = b.re / b.im, den = b.re * t + b.im;
-    return {(a.re * t + a.im) / den, (a.im * t - a.re) / den};
+    const double t = b.re / b.im, inv = 1.0 / (b.re * t + b.im);
+    return {(a.re * t + a.im) * inv, (a.im * t - a.re) * inv};
 }
 __device__ __forceinline__ Cx cexp(Cx z)
 {
@@ -157,21 +161,29 @@ __device__ uint32_t panels_from(const double *bound, double EG, double K)
     return 0u;
 }
 
-__global__ __launch_bounds__(BLOCK) void geo_node_kernel(const GeoControl g, const double *bound,
-                                                         const double *out, double *partials)
+// Gauss-Legendre nodes of the integral, two transforms per node.  With
+// `fixed` panels the three threads after the nodes evaluate the modulus bound
+// at v = fixed (out[4], out[5]) and E[G] (out[2]); otherwise the panel count
+// comes from the bound table of geo_bound_kernel.
+__global__ __launch_bounds__(BLOCK) void geo_node_kernel(const GeoControl g, uint32_t fixed,
+                                                         const double *bound, double *out,
+                                                         double *partials)
 {
     __shared__ double red[BLOCK / 64];
-    const uint32_t panels = panels_from(bound, out[2], g.K);
+    const uint32_t panels = fixed ? fixed : panels_from(bound, out[2], g.K);
     const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+    const uint32_t n_node_threads = 32u * panels;
     double val = 0.0;
-    if ((uint64_t)blockIdx.x * BLOCK < 32ull * panels) { // wave-uniform per block
-        if (t < 32u * panels) {
-            const uint32_t node = t >> 1, panel = node >> 4, j = node & 15;
-            const double x = j < 8 ? -g.gl_x[7 - j] : g.gl_x[j - 8];
-            const double w = j < 8 ? g.gl_w[7 - j] : g.gl_w[j - 8];
-            const double v = (double)panel + 0.5 + 0.5 * x;
-            val = 0.5 * w * integrand_part(g, v, (int)(t & 1));
-        }
+    if (t < n_node_threads) {
+        const uint32_t node = t >> 1, panel = node >> 4, j = node & 15;
+        const double x = j < 8 ? -g.gl_x[7 - j] : g.gl_x[j - 8];
+        const double w = j < 8 ? g.gl_w[7 - j] : g.gl_w[j - 8];
+        const double v = (double)panel + 0.5 + 0.5 * x;
+        val = 0.5 * w * integrand_part(g, v, (int)(t & 1));
+    } else if (fixed && t < n_node_threads + 2) {
+        out[4 + (t - n_node_threads)] = bound_part(g, (double)fixed, (int)(t - n_node_threads));
+    } else if (fixed && t == n_node_threads + 2) {
+        out[2] = exp(log_transform(g, Cx{1.0, 0.0}).re); // E[G]
     }
     const double s = wave_sum(val);
     if ((threadIdx.x & 63) == 0)
@@ -186,12 +198,13 @@ __global__ __launch_bounds__(BLOCK) void geo_node_kernel(const GeoControl g, con
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void geo_finish_kernel(const GeoControl g, const double *bound,
+__global__ __launch_bounds__(BLOCK) void geo_finish_kernel(const GeoControl g, uint32_t fixed,
+                                                           uint32_t n_blocks, const double *bound,
                                                            const double *partials, double *out)
 {
     __shared__ double red[BLOCK];
     double s = 0.0;
-    for (uint32_t b = threadIdx.x; b < GEO_NODE_BLOCKS; b += BLOCK)
+    for (uint32_t b = threadIdx.x; b < n_blocks; b += BLOCK)
         s += partials[b];
     red[threadIdx.x] = s;
     __syncthreads();
@@ -203,31 +216,43 @@ __global__ __launch_bounds__(BLOCK) void geo_finish_kernel(const GeoControl g, c
     if (threadIdx.x == 0) {
         const double EG = out[2], I = red[0];
         const double D = exp(-g.r * g.T);
-        const uint32_t panels = panels_from(bound, EG, g.K);
+        const bool ok = fixed ? out[4] + out[5] <= GEO_TOL * (EG + g.K)
+                              : panels_from(bound, EG, g.K) != 0u;
         const double call = D * (0.5 * (EG - g.K) + I / M_PI);
         const double nan = __builtin_nan("");
-        out[0] = panels ? call : nan;
-        out[1] = panels ? call - D * (EG - g.K) : nan;
+        out[0] = ok ? call : nan;
+        out[1] = ok ? call - D * (EG - g.K) : nan;
         out[3] = I;
     }
 }
 
 } // namespace
 
-hipError_t launch_geo_bound(const GeoControl &g, double *buf, hipStream_t stream)
+uint32_t geo_node_blocks() { return GEO_NODE_BLOCKS; }
+
+hipError_t launch_geo_price_fixed(const GeoControl &g, double *partials, double *buf,
+                                  hipStream_t stream)
 {
-    hipLaunchKernelGGL(geo_bound_kernel, dim3(1), dim3(64), 0, stream, g, buf, buf + GEO_OUT);
+    static_assert((32u * GEO_MAX_FIXED_PANELS + 3u + BLOCK - 1) / BLOCK <= GEO_NODE_BLOCKS,
+                  "fixed range within the partials buffer");
+    if (g.n_panels < 1 || g.n_panels > GEO_MAX_FIXED_PANELS)
+        return hipErrorInvalidValue;
+    const uint32_t blocks = (32u * g.n_panels + 3u + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(geo_node_kernel, dim3(blocks), dim3(BLOCK), 0, stream, g, g.n_panels,
+                       (const double *)buf, buf + GEO_OUT, partials);
+    hipLaunchKernelGGL(geo_finish_kernel, dim3(1), dim3(BLOCK), 0, stream, g, g.n_panels, blocks,
+                       (const double *)buf, (const double *)partials, buf + GEO_OUT);
     return hipGetLastError();
 }
 
-uint32_t geo_node_blocks() { return GEO_NODE_BLOCKS; }
-
-hipError_t launch_geo_price(const GeoControl &g, double *partials, double *buf,
-                            hipStream_t stream)
+hipError_t launch_geo_price_search(const GeoControl &g, double *partials, double *buf,
+                                   hipStream_t stream)
 {
-    hipLaunchKernelGGL(geo_node_kernel, dim3(GEO_NODE_BLOCKS), dim3(BLOCK), 0, stream, g, buf,
-                       buf + GEO_OUT, partials);
-    hipLaunchKernelGGL(geo_finish_kernel, dim3(1), dim3(BLOCK), 0, stream, g, buf, partials,
+    hipLaunchKernelGGL(geo_bound_kernel, dim3(1), dim3(64), 0, stream, g, buf, buf + GEO_OUT);
+    hipLaunchKernelGGL(geo_node_kernel, dim3(GEO_NODE_BLOCKS), dim3(BLOCK), 0, stream, g, 0u,
+                       (const double *)buf, buf + GEO_OUT, partials);
+    hipLaunchKernelGGL(geo_finish_kernel, dim3(1), dim3(BLOCK), 0, stream, g, 0u,
+                       GEO_NODE_BLOCKS, (const double *)buf, (const double *)partials,
                        buf + GEO_OUT);
     return hipGetLastError();
 }

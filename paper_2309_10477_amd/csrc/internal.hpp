@@ -106,7 +106,7 @@ struct GeoControl {
     double dt;                 // fixing time of step k is k dt
     const uint32_t *steps;     // fixing steps (device), or null = every step 1..n_fix
     uint32_t n_fix;
-    uint32_t n_panels;         // Gauss-Legendre panels of unit width on [0, n_panels]
+    uint32_t n_panels;         // first range: unit Gauss-Legendre panels on [0, n_panels]
     double gl_x[8], gl_w[8];   // positive 16-point Gauss-Legendre nodes and weights
 };
 
@@ -205,17 +205,21 @@ hipError_t launch_reduce(const PriceLaunch &L, double *rep_sums, hipStream_t str
 
 // Geometric-average control, in one device buffer `buf` of GEO_BUF_DOUBLES:
 // [0, 2 GEO_BOUND_POINTS) the modulus bounds |M(1 + iv)| / v and K |M(iv)| / v
-// at v = 2^k (M the transform of ln G), then at GEO_OUT the discounted call
-// and put prices of G, E[G] and the Gil-Pelaez integral (prices NaN when the
-// transform has not decayed by v = 2^14).  `partials` (device
-// [geo_node_blocks()]) holds one double per block of the node kernel.
+// at v = 2^k (M the transform of ln G; search only), then at GEO_OUT the
+// discounted call and put prices of G, E[G], the Gil-Pelaez integral and the
+// two bounds at the end of the fixed range.  The prices are NaN when the
+// transform has not decayed by the end of the range (fixed: g.n_panels, at
+// most GEO_MAX_FIXED_PANELS; search: 2^14).  `partials` (device [geo_node_blocks()]) holds one double per
+// block of the node kernel.
 constexpr int GEO_BOUND_POINTS = 15;
 constexpr int GEO_OUT = 2 * GEO_BOUND_POINTS;
-constexpr int GEO_BUF_DOUBLES = GEO_OUT + 4;
-hipError_t launch_geo_bound(const GeoControl &g, double *buf, hipStream_t stream);
+constexpr int GEO_BUF_DOUBLES = GEO_OUT + 6;
+constexpr uint32_t GEO_MAX_FIXED_PANELS = 4096;
 uint32_t geo_node_blocks();
-hipError_t launch_geo_price(const GeoControl &g, double *partials, double *buf,
-                            hipStream_t stream);
+hipError_t launch_geo_price_fixed(const GeoControl &g, double *partials, double *buf,
+                                  hipStream_t stream);
+hipError_t launch_geo_price_search(const GeoControl &g, double *partials, double *buf,
+                                   hipStream_t stream);
 
 // Fills the [N][STEP_WEIGHTS] fixing weights of `L` (its precision) at
 // L.step_weights.

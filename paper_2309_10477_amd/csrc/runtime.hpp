@@ -28,6 +28,10 @@ struct heston_ctx {
     double *host_sums = nullptr; // pinned
     size_t host_sums_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // side stream (default priority, created on first use) on which the
+    // geometric control's price runs beside the path kernel
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace heston {

@@ -140,9 +140,15 @@ def test_sobol_replicates(hm, ctx, prec):
 
 @pytest.mark.parametrize("p", [PB.replace(T=0.1, sigma=1.0, kappa=0.5),
                                PB.replace(T=5.0, rho=0.3, v0=0.09),
-                               PP.replace(rho=-0.9)],
-                         ids=["short-high-volvol", "long-positive-rho", "paper-rho-0.9"])
+                               PP.replace(rho=-0.9),
+                               PB.replace(T=0.01, v0=0.01, theta=0.01, sigma=0.1),
+                               PB.replace(v0=0.01, theta=0.01, sigma=2.0, kappa=1.0)],
+                         ids=["short-high-volvol", "long-positive-rho", "paper-rho-0.9",
+                              "very-short-low-vol", "range-search"])
 def test_control_mean_across_parameters(hm, ctx, p):
+    """The last case's transform (vol of vol 2 over a variance level of 0.01)
+    decays far more slowly than the library's first range assumes, so the
+    library searches a longer one."""
     N = 48
     fix = tuple(range(4, 49, 4))
     for opt in (oracle.ASIAN_CALL, oracle.ASIAN_PUT):
