@@ -185,3 +185,149 @@ def price(p: Params, asian: bool, n_paths: int, seed: int, times=None, control_v
         b = c[0, 1] / c[1, 1]
         y = y - b * (X - EX)
     return float(y.mean()), float(y.std(ddof=1) / math.sqrt(n_paths))
+
+
+# --------------------------------------------------------------------------
+# Counter-based random inputs, for parity with the device sampler.  Block k of
+# exact step j of path p is Philox4x32-10 at counter (j, lo32 p, hi32 p,
+# 5 + 256 k) under key (lo32 seed, hi32 seed); a word w maps to the uniform
+# ((w >> 9) + 1/2) 2^-23.  Block 0: Box-Muller of words 0, 1 gives (Zv, Zs)
+# -- Zv enters the non-central chi-square, Zs the log-price -- word 2 the
+# uniform of the integrated-variance inversion, word 3 the uniform of the
+# Poisson count (d <= 1).  Blocks 1, 2, ...: attempt k of the gamma sampler
+# (the first Box-Muller normal of words 0, 1 and the acceptance uniform of
+# word 2); word 3 of block 1 is the uniform that lowers a shape below one.
+
+BK_TAG = 5
+MAX_GAMMA_ATTEMPTS = 64
+MAX_POISSON_MEAN = 700.0
+
+
+def _u(w) -> float:
+    return ((int(w) >> 9) + 0.5) * 2.0 ** -23
+
+
+def draw_block(seed: int, path: int, step: int, k: int) -> np.ndarray:
+    from . import philox
+    ctr = [[step, path & 0xFFFFFFFF, path >> 32, BK_TAG + (k << 8)]]
+    key = [[seed & 0xFFFFFFFF, seed >> 32]]
+    return philox(np.array(ctr, dtype=np.uint32), np.array(key, dtype=np.uint32))[0]
+
+
+def _box_muller(w0, w1):
+    r = math.sqrt(-2.0 * math.log(_u(w0)))
+    a = 2.0 * math.pi * _u(w1)
+    return r * math.cos(a), r * math.sin(a)
+
+
+def gamma_counter(alpha: float, seed: int, path: int, step: int) -> float:
+    """Gamma(alpha, 1) by Marsaglia and Tsang (ACM TOMS 26(3), 2000): with
+    d = a - 1/3, c = 1/sqrt(9 d), a normal x and v = (1 + c x)^3 > 0, accept d v
+    when ln U < x^2/2 + d - d v + d ln v (the full test, no squeeze).  For
+    alpha < 1, a = alpha + 1 and the draw is multiplied by U^(1/alpha).
+    NaN after MAX_GAMMA_ATTEMPTS rejections."""
+    a = alpha + 1.0 if alpha < 1.0 else alpha
+    d = a - 1.0 / 3.0
+    c = 1.0 / math.sqrt(9.0 * d)
+    g = math.nan
+    boost = None
+    for k in range(1, MAX_GAMMA_ATTEMPTS + 1):
+        w = draw_block(seed, path, step, k)
+        if k == 1:
+            boost = _u(w[3])
+        x = _box_muller(w[0], w[1])[0]
+        v = 1.0 + c * x
+        if v <= 0.0:
+            continue
+        v = v * v * v
+        if math.log(_u(w[2])) < 0.5 * x * x + d - d * v + d * math.log(v):
+            g = d * v
+            break
+    if alpha < 1.0:
+        g *= boost ** (1.0 / alpha)
+    return g
+
+
+def poisson_inverse(mu: float, u: float) -> float:
+    """Smallest k with u <= P(N <= k), N ~ Poisson(mu), by summing the
+    probabilities upwards from k = 0; NaN for mu above MAX_POISSON_MEAN."""
+    if mu > MAX_POISSON_MEAN:
+        return math.nan
+    k, pk = 0, math.exp(-mu)
+    F = pk
+    cap = int(mu + 40.0 * math.sqrt(mu) + 100.0)
+    while u > F and k < cap:
+        k += 1
+        pk *= mu / k
+        F += pk
+    return float(k)
+
+
+def sample_vt_counter(p: Params, vu: float, dt: float, seed: int, path: int, step: int):
+    """V_t given V_u on the counter-based inputs; also returns (Zs, U) of block 0."""
+    e = math.exp(-p.kappa * dt)
+    c = p.sigma ** 2 * (1.0 - e) / (4.0 * p.kappa)
+    d = 4.0 * p.kappa * p.theta / p.sigma ** 2
+    lam = vu * e / c
+    w = draw_block(seed, path, step, 0)
+    zv, zs = _box_muller(w[0], w[1])
+    if d > 1.0:
+        x = 2.0 * gamma_counter(0.5 * (d - 1.0), seed, path, step) + (zv + math.sqrt(lam)) ** 2
+    else:
+        n = poisson_inverse(0.5 * lam, _u(w[3]))
+        x = 2.0 * gamma_counter(0.5 * d + n, seed, path, step) if n == n else math.nan
+    return c * x, zs, _u(w[2])
+
+
+def simulate_counter(p: Params, opt_type: int, n_steps: int, seed: int, first: int = 0,
+                     n_paths: int = 1, fixings=None, integral: bool = False):
+    """Exact paths on the counter-based inputs: records [n_paths, 6] = (S_T, V_T,
+    X, pay, pw_delta, pw_rho) as oracle.simulate, over n_steps exact steps of
+    T / n_steps (the fixing dates are steps, as there).  With `integral`, also
+    the integral of V over [0, T] per path."""
+    from . import ASIAN_CALL, EURO_CALL, GEO_ASIAN_CALL, GEO_ASIAN_PUT
+    N = n_steps
+    D = p.T / N
+    fix = set(range(1, N + 1)) if fixings is None else set(int(f) for f in fixings)
+    asian = opt_type >= 2
+    geo = opt_type in (GEO_ASIAN_CALL, GEO_ASIAN_PUT)
+    call = opt_type in (EURO_CALL, ASIAN_CALL, GEO_ASIAN_CALL)
+    n_fix = len(fix) if asian else 1
+    iv = IntegratedVariance(p, D)
+    disc = math.exp(-p.r * p.T)
+    out = np.empty((n_paths, 6))
+    total = np.zeros(n_paths)
+    for i in range(n_paths):
+        path = first + i
+        x, V, A, B = 0.0, p.v0, 0.0, 0.0
+        for j in range(N):
+            vt, zs, uI = sample_vt_counter(p, V, D, seed, path, j)
+            I = iv.sample(V, vt, uI) if vt == vt else math.nan
+            total[i] += I
+            isq = (vt - V - p.kappa * p.theta * D + p.kappa * I) / p.sigma
+            x += p.r * D - 0.5 * I + p.rho * isq \
+                + math.sqrt(1.0 - p.rho ** 2) * math.sqrt(max(I, 0.0)) * zs
+            V = vt
+            if asian and (j + 1) in fix:
+                t = (j + 1) * D
+                if geo:
+                    A += math.log(p.S0) + x
+                    B += t
+                else:
+                    S = p.S0 * math.exp(x)
+                    A += S
+                    B += t * S
+        S = p.S0 * math.exp(x)
+        X = math.exp(A / n_fix) if geo else A / n_fix if asian else S
+        if geo:
+            B = X * B
+        sgn = 1.0 if call else -1.0
+        itm = sgn * (X - p.K) > 0.0
+        pay = disc * sgn * (X - p.K) if itm else 0.0
+        dpw = sgn * disc * X / p.S0 if itm else 0.0
+        if asian:
+            rpw = disc * (sgn * B / n_fix - p.T * sgn * (X - p.K)) if itm else 0.0
+        else:
+            rpw = sgn * disc * p.K * p.T if itm else 0.0
+        out[i] = (S, V, X, pay, dpw, rpw)
+    return (out, total) if integral else out
