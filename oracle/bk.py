@@ -71,21 +71,31 @@ class IntegratedVariance:
             - math.log(p.kappa) - np.log(1.0 - eg)
         t2 = (vu + vt) / s2 * (p.kappa * (1.0 + ek) / (1.0 - ek) - g * (1.0 + eg) / (1.0 - eg))
         r = math.sqrt(vu * vt)
+        # ln of z(a) = 4 g e^{-g D/2} / (sigma^2 (1 - e^{-g D})) (times r), summed
+        # from its factors: no underflow where e^{-g D/2} would vanish, and its
+        # imaginary part is an argument of z continuous along a >= 0 (zero at
+        # a = 0: arg g, -Im(g) D/2 and arg(1 - e^{-g D}) each vary
+        # continuously, the last with 1 - e^{-g D} in the right half-plane)
+        lz0 = np.log(4.0 * g) - 0.5 * g * D - np.log(s2 * (1.0 - eg))
+        lk0 = math.log(4.0 * p.kappa) - 0.5 * p.kappa * D - math.log(s2 * (1.0 - ek))
         if r == 0.0:
             # I_nu(z) ~ (z/2)^nu / Gamma(nu+1) as z -> 0: the ratio is (z_g / z_k)^nu
-            zg = 4.0 * g * np.exp(-0.5 * g * D) / (s2 * (1.0 - eg))
-            zk = 4.0 * p.kappa * math.exp(-0.5 * p.kappa * D) / (s2 * (1.0 - ek))
-            t3 = nu * (np.log(zg) - math.log(zk))
-            return t1 + t2 + t3
-        zg = r * 4.0 * g * np.exp(-0.5 * g * D) / (s2 * (1.0 - eg))
-        zk = r * 4.0 * p.kappa * math.exp(-0.5 * p.kappa * D) / (s2 * (1.0 - ek))
-        ang = np.angle(zg)
-        wound = np.unwrap(np.concatenate([[0.0], ang]))[1:]
-        m = np.rint((wound - ang) / (2.0 * np.pi))
-        # I_nu on the principal branch, exponentially scaled to avoid overflow
-        lg = np.log(special.ive(nu, zg)) + np.abs(zg.real) + 2j * np.pi * m * nu
-        lk = math.log(special.ive(nu, zk)) + abs(zk)
-        return t1 + t2 + lg - lk
+            return t1 + t2 + nu * (lz0 - lk0)
+        lzg, lzk = math.log(r) + lz0, math.log(r) + lk0
+        zg, zk = np.exp(lzg), math.exp(lzk)
+
+        def log_i(lz, z):
+            # ln I_nu(z) on the branch of lz: the principal value of ive (scaled
+            # by e^{-|Re z|}) plus nu times the turns of Im lz beyond arg z; below
+            # |z| = 1e-30 the leading term of the series
+            z = np.asarray(z)
+            small = np.abs(z) < 1e-30
+            zs = np.where(small, 1.0, z)
+            turns = np.imag(lz) - np.angle(zs)
+            big = np.log(special.ive(nu, zs)) + np.abs(zs.real) + 1j * nu * turns
+            return np.where(small, nu * (lz - math.log(2.0)) - special.gammaln(nu + 1.0), big)
+
+        return t1 + t2 + log_i(lzg, zg) - log_i(lzk, zk).real
 
     def moments(self, vu: float, vt: float):
         """Conditional mean and standard deviation from log Phi near 0:
