@@ -96,6 +96,16 @@ enum { HESTON_RNG_PHILOX = 0, HESTON_RNG_SOBOL_BRIDGE = 1 };
  * Philox inputs, sigma > 0 and theta > 0; its step j takes one Philox block
  * with counter (j, lo32 path, hi32 path, 4): Box-Muller of words 0, 1 for the
  * price and variance normals, word 2 for the exponential-branch uniform.
+ * HESTON_EXACT is the paper's exact simulation (algorithm "Broadie and Kaya
+ * exact simulation algorithm"): each of the n_steps steps of length T/n_steps
+ * draws V_t from its non-central chi-square law given V_u, the integral of V
+ * over the step by inverting its conditional characteristic function, and
+ * ln S from both; no discretisation bias.  It runs in FP64 with Philox inputs
+ * and pathwise Greeks only, needs sigma > 0 and theta > 0, and takes at most
+ * HESTON_EXACT_MAX_STEPS steps; its inputs are laid out per (step, path) as
+ * Philox blocks with counter (step, lo32 path, hi32 path, 5 + 256 k).  Paths
+ * whose draws leave the sampler's numerical range (see exact_kernel.hip) make
+ * the call fail with HESTON_UNSUPPORTED.
  * Adjoint calls, batches and the server use the Milstein schemes only. */
 enum {
     HESTON_FULL_TRUNCATION = 0,
@@ -104,8 +114,10 @@ enum {
     HESTON_EULER_FULL_TRUNCATION = 3,
     HESTON_EULER_ABSORPTION = 4,
     HESTON_PARTIAL_TRUNCATION = 5,
-    HESTON_REFLECTION = 6
+    HESTON_REFLECTION = 6,
+    HESTON_EXACT = 7
 };
+#define HESTON_EXACT_MAX_STEPS 4096
 /* Greek estimators (bit mask). */
 enum {
     HESTON_GREEKS_PATHWISE = 1u,   /* paper's pathwise Delta and Rho              */
@@ -165,7 +177,7 @@ typedef struct heston_opts {
     int32_t rng;          /* HESTON_RNG_PHILOX (default) or HESTON_RNG_SOBOL_BRIDGE */
     int32_t scheme;       /* HESTON_FULL_TRUNCATION (default), HESTON_ABSORPTION, HESTON_QE,
                              HESTON_EULER_FULL_TRUNCATION, HESTON_EULER_ABSORPTION,
-                             HESTON_PARTIAL_TRUNCATION or HESTON_REFLECTION */
+                             HESTON_PARTIAL_TRUNCATION, HESTON_REFLECTION or HESTON_EXACT */
     uint32_t greeks;      /* HESTON_GREEKS_* mask; default PATHWISE | BUMP_FUSED */
     uint32_t qmc_replicates; /* Sobol: R digitally shifted replicates; n_paths must
                                 be a multiple of R (points per replicate = n_paths/R) */

@@ -23,7 +23,8 @@ EURO_CALL, EURO_PUT, ASIAN_CALL, ASIAN_PUT, GEO_ASIAN_CALL, GEO_ASIAN_PUT = 0, 1
 FP64, FP32 = 0, 1
 PHILOX, SOBOL_BRIDGE = 0, 1
 (FULL_TRUNCATION, ABSORPTION, QE, EULER_FULL_TRUNCATION, EULER_ABSORPTION, PARTIAL_TRUNCATION,
- REFLECTION) = 0, 1, 2, 3, 4, 5, 6
+ REFLECTION, EXACT) = 0, 1, 2, 3, 4, 5, 6, 7
+EXACT_MAX_STEPS = 4096
 GREEKS_PATHWISE, GREEKS_BUMP_FUSED, GREEKS_BUMP_PLAIN = 1, 2, 4
 ABI_VERSION = 2
 CONTROL_NONE, CONTROL_GEOMETRIC = 0, 1

@@ -153,6 +153,28 @@ bool bridge_program(uint32_t N, BridgePlan &plan)
 }
 
 
+// Device bitmask of the Asian fixing steps (bit j for step j), or null when
+// every step fixes (or the option is European).
+static heston_status upload_fix_bits(heston_ctx *c, const Request &q, const uint32_t **out)
+{
+    const heston_opts &o = q.o;
+    *out = nullptr;
+    if (q.type < 2 || !o.fixing_steps)
+        return HESTON_OK;
+    const size_t words = (q.n_steps + 1 + 31) / 32;
+    std::vector<uint32_t> bits(words, 0u);
+    for (uint32_t i = 0; i < o.n_fixings; ++i)
+        bits[o.fixing_steps[i] >> 5] |= 1u << (o.fixing_steps[i] & 31u);
+    heston_status st = reserve(c, c->fix_bits, words * 4);
+    if (st != HESTON_OK)
+        return st;
+    HIP_TRY(hipMemcpyAsync(c->fix_bits.ptr, bits.data(), words * 4, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream)); // `bits` is released at return
+    *out = (const uint32_t *)c->fix_bits.ptr;
+    return HESTON_OK;
+}
+
 heston_status check_request(const Request &q)
 {
     heston_status st = check_params(&q.p);
@@ -171,8 +193,22 @@ heston_status check_request(const Request &q)
         return fail(HESTON_INVALID_ARGUMENT, "unknown precision");
     if (o.rng != HESTON_RNG_PHILOX && o.rng != HESTON_RNG_SOBOL_BRIDGE)
         return fail(HESTON_INVALID_ARGUMENT, "unknown rng");
-    if (o.scheme < HESTON_FULL_TRUNCATION || o.scheme > HESTON_REFLECTION)
+    if (o.scheme < HESTON_FULL_TRUNCATION || o.scheme > HESTON_EXACT)
         return fail(HESTON_INVALID_ARGUMENT, "unknown scheme");
+    if (o.scheme == HESTON_EXACT) {
+        if (o.precision != HESTON_FP64)
+            return fail(HESTON_UNSUPPORTED, "exact simulation runs in FP64");
+        if (o.rng != HESTON_RNG_PHILOX)
+            return fail(HESTON_UNSUPPORTED, "exact simulation draws Philox inputs only");
+        if ((o.greeks & ~(uint32_t)HESTON_GREEKS_PATHWISE) != 0)
+            return fail(HESTON_UNSUPPORTED, "exact simulation gives pathwise Greeks only");
+        if (o.control_variate != HESTON_CONTROL_NONE)
+            return fail(HESTON_UNSUPPORTED, "exact simulation takes no control variate");
+        if (!(q.p.sigma > 0) || !(q.p.theta > 0))
+            return fail(HESTON_INVALID_ARGUMENT, "exact simulation needs sigma > 0 and theta > 0");
+        if (q.n_steps > HESTON_EXACT_MAX_STEPS)
+            return fail(HESTON_UNSUPPORTED, "more exact steps than supported");
+    }
     if (o.scheme == HESTON_QE) {
         if (o.rng != HESTON_RNG_PHILOX)
             return fail(HESTON_UNSUPPORTED, "the QE scheme draws Philox inputs only");
@@ -285,19 +321,10 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
             L.fix_step_sum += (double)o.fixing_steps[i];
     else
         L.fix_step_sum = 0.5 * (double)q.n_steps * ((double)q.n_steps + 1.0);
-    L.fix_bits = nullptr;
-    if (asian && o.fixing_steps) {
-        const size_t words = (q.n_steps + 1 + 31) / 32;
-        std::vector<uint32_t> bits(words, 0u);
-        for (uint32_t i = 0; i < o.n_fixings; ++i)
-            bits[o.fixing_steps[i] >> 5] |= 1u << (o.fixing_steps[i] & 31u);
-        heston_status st = reserve(c, c->fix_bits, words * 4);
+    {
+        heston_status st = upload_fix_bits(c, q, &L.fix_bits);
         if (st != HESTON_OK)
             return st;
-        HIP_TRY(hipMemcpyAsync(c->fix_bits.ptr, bits.data(), words * 4, hipMemcpyHostToDevice,
-                               c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream)); // `bits` is released at return
-        L.fix_bits = (const uint32_t *)c->fix_bits.ptr;
     }
     if (asian && !geo) {
         const size_t real = o.precision == HESTON_FP64 ? 8 : 4;
@@ -651,7 +678,7 @@ heston_status heston_ctx_destroy(heston_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift, &c->sobol_hi, &c->sobol_perm, &c->sobol_dir12,
                       &c->bridge_start, &c->bridge_ops, &c->pay, &c->bump_partials,
-                      &c->geo_buf, &c->geo_partials, &c->geo_steps,
+                      &c->geo_buf, &c->geo_partials, &c->geo_steps, &c->exact_scratch,
                       &c->bump_sums, &c->step_w, &c->batch_opts, &c->batch_items, &c->batch_partials,
                       &c->batch_sums, &c->batch_counter, &c->batch_scratch})
         if (b->ptr)
@@ -810,6 +837,62 @@ static void cv_combine(const double *s, const PriceLaunch &L, bool reps, uint64_
     r.valid_mask |= HESTON_VALID_CONTROL;
 }
 
+// Exact simulation of paths first .. first+count-1: sums[EXACT_REC] receives
+// the FP64 estimator sums (price, pathwise Delta and Rho as (sum, sum of
+// squares)) and, at N_ACC, the number of failed paths.
+static heston_status run_exact(heston_ctx *c, const Request &q, uint64_t first, uint64_t count,
+                               double *dump, double *sums, float *ms)
+{
+    const heston_params &p = q.p;
+    ExactLaunch E;
+    std::memset(&E, 0, sizeof(E));
+    E.S0 = p.S0; E.K = p.K; E.r = p.r; E.T = p.T; E.v0 = p.v0;
+    E.kappa = p.kappa; E.theta = p.theta; E.sigma = p.sigma; E.rho = p.rho;
+    E.rho_bar = std::sqrt(std::max(0.0, 1.0 - p.rho * p.rho));
+    E.D = p.T / q.n_steps;
+    const double s2 = p.sigma * p.sigma;
+    const double ek = std::exp(-p.kappa * E.D);
+    E.ekD = ek;
+    E.c = s2 * (1.0 - ek) / (4.0 * p.kappa);
+    E.d = 4.0 * p.kappa * p.theta / s2;
+    E.nu = 2.0 * p.kappa * p.theta / s2 - 1.0;
+    E.kappa2 = p.kappa * p.kappa;
+    E.two_sigma2 = 2.0 * s2;
+    E.sigma2 = s2;
+    E.inv_sigma2 = 1.0 / s2;
+    E.t1_const = std::log(1.0 - ek) - std::log(p.kappa) + 0.5 * p.kappa * E.D;
+    E.coth_k = p.kappa * (1.0 + ek) / (1.0 - ek);
+    E.log_zk_scale = std::log(4.0 * p.kappa) - 0.5 * p.kappa * E.D - std::log(s2 * (1.0 - ek));
+    E.log4_over_sigma2 = std::log(4.0 / s2);
+    E.opt_type = q.type;
+    E.n_steps = q.n_steps;
+    E.n_fix = q.type >= 2 ? (q.o.fixing_steps ? q.o.n_fixings : q.n_steps) : 1;
+    E.seed = q.seed;
+    E.first_path = first;
+    E.n_paths = count;
+    E.n_lanes = (uint32_t)std::min<uint64_t>((count + BLOCK - 1) / BLOCK * BLOCK, EXACT_MAX_LANES);
+    heston_status st;
+    if ((st = upload_fix_bits(c, q, &E.fix_bits)) != HESTON_OK ||
+        (st = reserve(c, c->exact_scratch, (size_t)EXACT_MAX_GRID * E.n_lanes * 8)) != HESTON_OK ||
+        (st = reserve(c, c->partials, (size_t)(E.n_lanes / BLOCK) * EXACT_REC * 8)) != HESTON_OK ||
+        (st = reserve(c, c->rep_sums, EXACT_REC * 8)) != HESTON_OK)
+        return st;
+    E.scratch = (double *)c->exact_scratch.ptr;
+    E.partials = (double *)c->partials.ptr;
+    E.dump = dump;
+    HIP_TRY(hipEventRecord(c->ev0, c->stream));
+    HIP_TRY(launch_exact(E, c->stream));
+    HIP_TRY(hipEventRecord(c->ev1, c->stream));
+    HIP_TRY(launch_reduce_rows(E.partials, E.n_lanes / BLOCK, EXACT_REC,
+                               (double *)c->rep_sums.ptr, c->stream));
+    HIP_TRY(hipMemcpyAsync(sums, c->rep_sums.ptr, EXACT_REC * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (ms)
+        HIP_TRY(hipEventElapsedTime(ms, c->ev0, c->ev1));
+    return HESTON_OK;
+}
+
 heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
                                      heston_option_type type, uint64_t n_paths, uint32_t n_steps,
                                      uint64_t seed, const heston_opts *opts, heston_result *out)
@@ -823,6 +906,27 @@ heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
     if (st != HESTON_OK)
         return st;
     DeviceGuard g(c->device);
+    if (q.o.scheme == HESTON_EXACT) {
+        double sums[EXACT_REC];
+        float ms = 0;
+        if ((st = run_exact(c, q, 0, n_paths, nullptr, sums, &ms)) != HESTON_OK)
+            return st;
+        if (sums[N_ACC] > 0)
+            return fail(HESTON_UNSUPPORTED,
+                        std::to_string((uint64_t)sums[N_ACC]) +
+                            " paths left the exact sampler's range (Bessel series, grid length, "
+                            "Poisson mean or gamma rejections)");
+        heston_result r;
+        std::memset(&r, 0, sizeof(r));
+        r.price = est_from((double)n_paths, sums[0], sums[1]);
+        r.pw_delta = est_from((double)n_paths, sums[2], sums[3]);
+        r.pw_rho = est_from((double)n_paths, sums[4], sums[5]);
+        r.n_paths = n_paths;
+        r.valid_mask = HESTON_VALID_PRICE | HESTON_VALID_PATHWISE;
+        r.device_ms = ms;
+        *out = r;
+        return HESTON_OK;
+    }
     if (q.o.greeks & HESTON_GREEKS_BUMP_PLAIN) {
         // five Greeks from four central bumps, each scenario revalued on its own
         const heston_bump bumps[4] = {{HESTON_P_S0, 1, q.o.bump_S0_rel},
@@ -944,6 +1048,10 @@ heston_status heston_dump_paths(heston_ctx *c, const heston_params *params,
     if (first + count < first)
         return fail(HESTON_INVALID_ARGUMENT, "dump range overflows");
     DeviceGuard g(c->device);
+    if (q.o.scheme == HESTON_EXACT) {
+        double sums[EXACT_REC];
+        return run_exact(c, q, first, count, out_dev, sums, nullptr);
+    }
     PriceLaunch L;
     if ((st = plan(c, q, first, count, L)) != HESTON_OK)
         return st;

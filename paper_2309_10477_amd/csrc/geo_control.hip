@@ -28,6 +28,7 @@
 
 #include <cmath>
 
+#include "cplx.hpp"
 #include "device_math.hpp"
 #include "internal.hpp"
 
@@ -40,48 +41,6 @@ static_assert(2 * GEO_BOUND_POINTS < 64, "one wave evaluates every bound and E[G
 constexpr uint32_t GEO_NODE_THREADS = 32u << GEO_MAX_LOG2_PANELS; // 16 nodes x 2 transforms
 constexpr uint32_t GEO_NODE_BLOCKS = GEO_NODE_THREADS / BLOCK;
 constexpr double GEO_TOL = 1e-15;
-
-struct Cx {
-    double re, im;
-};
-__device__ __forceinline__ Cx operator+(Cx a, Cx b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ Cx operator-(Cx a, Cx b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ Cx operator*(Cx a, Cx b)
-{
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-__device__ __forceinline__ Cx operator*(Cx a, double s) { return {a.re * s, a.im * s}; }
-// Smith's division (no overflow of |b|^2 for large operands), two real
-// divisions.
-__device__ __forceinline__ Cx operator/(Cx a, Cx b)
-{
-    if (fabs(b.re) >= fabs(b.im)) {
-        const double t = b.im / b.re, inv = 1.0 / (b.re + b.im * t);
-        return {(a.re + a.im * t) * inv, (a.im - a.re * t) * inv};
-    }
-    const double t = b.re / b.im, inv = 1.0 / (b.re * t + b.im);
-    return {(a.re * t + a.im) * inv, (a.im * t - a.re) * inv};
-}
-__device__ __forceinline__ Cx cexp(Cx z)
-{
-    double s, c;
-    sincos(z.im, &s, &c);
-    const double e = exp(z.re);
-    return {e * c, e * s};
-}
-// Principal branch.
-__device__ __forceinline__ Cx clog(Cx z) { return {log(hypot(z.re, z.im)), atan2(z.im, z.re)}; }
-// Principal square root (non-negative real part).
-__device__ __forceinline__ Cx csqrt(Cx z)
-{
-    const double m = hypot(z.re, z.im);
-    if (m == 0.0)
-        return {0.0, 0.0};
-    const double t = sqrt(0.5 * (m + fabs(z.re)));
-    if (z.re >= 0.0)
-        return {t, z.im / (2.0 * t)};
-    return {fabs(z.im) / (2.0 * t), copysign(t, z.im)};
-}
 
 __device__ __forceinline__ double fix_time(const GeoControl &g, uint32_t i)
 {

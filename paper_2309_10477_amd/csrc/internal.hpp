@@ -100,6 +100,38 @@ struct PriceLaunch {
     __host__ __device__ int acc_width() const { return cv ? N_ACC_CV : N_ACC; }
 };
 
+// Exact simulation (exact_kernel.hip): Broadie-Kaya steps of length D over
+// the n_steps grid, FP64.  Per-launch constants are computed on the host.
+constexpr uint32_t EXACT_COUNTER_TAG = 5u;      // fourth Philox counter word, plus 256 k
+constexpr int EXACT_MAX_GAMMA_ATTEMPTS = 64;
+constexpr double EXACT_MAX_POISSON_MEAN = 700.0;
+constexpr uint32_t EXACT_MAX_GRID = 16384;      // characteristic-function points per draw
+constexpr uint32_t EXACT_MAX_LANES = 65536;     // resident lanes (one wave per SIMD)
+constexpr int EXACT_REC = N_ACC + 2;            // partial record: estimator sums, failures, pad
+struct ExactLaunch {
+    double S0, K, r, T, v0, kappa, theta, sigma, rho, rho_bar;
+    double D;            // step length T / n_steps
+    double nu;           // 2 kappa theta / sigma^2 - 1 (Bessel order)
+    double d;            // 4 kappa theta / sigma^2 (degrees of freedom)
+    double c;            // sigma^2 (1 - e^{-kappa D}) / (4 kappa)
+    double ekD;          // e^{-kappa D}
+    double kappa2, two_sigma2, sigma2, inv_sigma2;
+    double t1_const;     // ln(1 - e^{-kappa D}) - ln kappa + kappa D / 2
+    double coth_k;       // kappa (1 + e^{-kappa D}) / (1 - e^{-kappa D})
+    double log_zk_scale; // ln(4 kappa e^{-kappa D/2} / (sigma^2 (1 - e^{-kappa D})))
+    double log4_over_sigma2; // ln(4 / sigma^2)
+    int opt_type;
+    uint32_t n_steps, n_fix;
+    const uint32_t *fix_bits; // device bitmask over steps 1..N, or null = every step
+    uint64_t seed;
+    uint64_t first_path, n_paths;
+    uint32_t n_lanes;         // lanes of the launch; lane l takes paths l, l + n_lanes, ...
+    double *scratch;          // device [EXACT_MAX_GRID][n_lanes]: Re Phi on the grid
+    double *partials;         // device [blocks][EXACT_REC]
+    double *dump;             // device [n_paths][DUMP_WIDTH] or null
+};
+hipError_t launch_exact(const ExactLaunch &L, hipStream_t stream);
+
 // Semi-analytic price of the geometric-average control (geo_control.hip).
 struct GeoControl {
     double lnS0, K, lnK, r, T, v0, kappa, theta, sigma, rho;

@@ -76,7 +76,8 @@ def test_enum_constants_match_binding():
              "HESTON_GEO_ASIAN_CALL", "HESTON_GEO_ASIAN_PUT", "HESTON_FP64", "HESTON_FP32", "HESTON_RNG_PHILOX", "HESTON_RNG_SOBOL_BRIDGE",
              "HESTON_FULL_TRUNCATION", "HESTON_ABSORPTION", "HESTON_QE",
              "HESTON_EULER_FULL_TRUNCATION", "HESTON_EULER_ABSORPTION",
-             "HESTON_PARTIAL_TRUNCATION", "HESTON_REFLECTION",
+             "HESTON_PARTIAL_TRUNCATION", "HESTON_REFLECTION", "HESTON_EXACT",
+             "HESTON_EXACT_MAX_STEPS",
              "HESTON_GREEKS_PATHWISE", "HESTON_GREEKS_BUMP_FUSED", "HESTON_GREEKS_BUMP_PLAIN"]
     src = ('#include "heston.h"\n#include <stdio.h>\nint main(void){printf("'
            + " ".join(["%d"] * len(names)) + '\\n", ' + ", ".join(f"(int){n}" for n in names)
@@ -90,5 +91,6 @@ def test_enum_constants_match_binding():
     want = [hm.ABI_VERSION, hm.EURO_CALL, hm.EURO_PUT, hm.ASIAN_CALL, hm.ASIAN_PUT, hm.GEO_ASIAN_CALL,
             hm.GEO_ASIAN_PUT, hm.FP64, hm.FP32, hm.PHILOX, hm.SOBOL_BRIDGE, hm.FULL_TRUNCATION, hm.ABSORPTION,
             hm.QE, hm.EULER_FULL_TRUNCATION, hm.EULER_ABSORPTION, hm.PARTIAL_TRUNCATION,
-            hm.REFLECTION, hm.GREEKS_PATHWISE, hm.GREEKS_BUMP_FUSED, hm.GREEKS_BUMP_PLAIN]
+            hm.REFLECTION, hm.EXACT, hm.EXACT_MAX_STEPS, hm.GREEKS_PATHWISE, hm.GREEKS_BUMP_FUSED,
+            hm.GREEKS_BUMP_PLAIN]
     assert got == want

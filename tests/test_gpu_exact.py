@@ -1,0 +1,143 @@
+"""GPU parity of the exact (Broadie-Kaya) sampler against the oracle.
+
+Per path: the kernel's dumped records against oracle.bk.simulate_counter on
+the same counter-based inputs.  Both sides invert the same conditional CDF of
+the integrated variance to |F - U| < 1e-13, but evaluate the characteristic
+function differently (a direct Bessel series on the device, scipy's ive in
+the oracle) and sum the CDF in different orders, so the integral agrees to
+about 1e-11 relative; the bar is 1e-9 relative to max(|oracle|, floor), the
+floors of the Milstein parity tests.  Reduced estimates equal the host sums of
+the oracle's records; prices agree with the characteristic-function price and
+the paper's exact-simulation Asian value within their errors.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import analytic, bk
+from workloads import BASE, PAPER, paper_fixing_steps
+
+pytestmark = pytest.mark.gpu
+
+PB = oracle.Params(**BASE)
+PP = oracle.Params(**PAPER)
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_10477_amd as hm
+    hm.lib()
+    return hm
+
+
+@pytest.fixture(scope="module")
+def ctx(hm):
+    c = hm.Context(0)
+    yield c
+    c.close()
+
+
+def close(name, g, o, floor):
+    err = np.abs(g - o) / np.maximum(np.abs(o), floor)
+    if not (err <= TOL).all():
+        i = int(np.nanargmax(np.where(np.isnan(err), np.inf, err)))
+        raise AssertionError(f"{name}: {int((~(err <= TOL)).sum())} paths off, worst {i}: "
+                             f"gpu {g[i]!r} oracle {o[i]!r} rel {err[i]:.3e}")
+
+
+def check(hm, ctx, p, opt, N, seed, n, first=0, fixings=None):
+    opts = hm.Options(scheme=hm.EXACT, greeks=hm.GREEKS_PATHWISE, fixings=fixings)
+    d = ctx.dump_paths(p.__dict__, opt, first + n, N, seed, first, n, opts).cpu().numpy()
+    rec, I = bk.simulate_counter(p, opt, N, seed, first, n, fixings, integral=True)
+    floors = {"S_T": p.S0, "V_T": max(p.v0, p.theta), "Sbar": p.S0, "pay": p.S0,
+              "pw_delta": 1.0, "pw_rho": p.K * p.T}
+    near = np.abs(rec[:, 2] - p.K) < 1e-6 * p.K
+    for k, name in enumerate(oracle.REC_FIELDS):
+        sel = ~near if name in ("pw_delta", "pw_rho") else slice(None)
+        close(name, d[sel, k], rec[sel, k], floors[name])
+    close("x_T", d[:, 14], np.log(rec[:, 0] / p.S0), 1.0)
+    close("int V", d[:, 15], I, max(p.v0, p.theta) * p.T)
+    assert np.isnan(d[:, 6:14]).all()
+    return d, rec
+
+
+@pytest.mark.parametrize("opt,N", [(oracle.EURO_CALL, 1), (oracle.EURO_PUT, 2),
+                                   (oracle.ASIAN_CALL, 4), (oracle.GEO_ASIAN_PUT, 4)])
+def test_base_parameters(hm, ctx, opt, N):
+    check(hm, ctx, PB, opt, N, 42, 300)
+
+
+def test_paper_parameters_quarterly_asian(hm, ctx):
+    """d = 1.27: the gamma shape (d - 1)/2 = 0.13 is raised and multiplied back."""
+    check(hm, ctx, PP, oracle.ASIAN_CALL, 4, 7, 300)
+
+
+def test_poisson_mixture_regime(hm, ctx):
+    """d <= 1: V_t from the Poisson mixture of central chi-squares."""
+    p = PP.replace(theta=0.004, sigma=0.7)
+    assert 4 * p.kappa * p.theta / p.sigma ** 2 <= 1
+    check(hm, ctx, p, oracle.EURO_CALL, 2, 3, 300)
+
+
+def test_explicit_fixings_and_wide_indices(hm, ctx):
+    check(hm, ctx, PB, oracle.ASIAN_PUT, 6, (9 << 40) | 5, 200, first=(1 << 32) + 11,
+          fixings=(2, 3, 6))
+
+
+def test_estimates_match_oracle_records(hm, ctx):
+    n, N, seed = 700, 2, 13
+    opts = hm.Options(scheme=hm.EXACT, greeks=hm.GREEKS_PATHWISE)
+    r = ctx.price_greeks(PB.__dict__, oracle.ASIAN_CALL, n, N, seed, opts)
+    rec = bk.simulate_counter(PB, oracle.ASIAN_CALL, N, seed, 0, n)
+    for k, name in ((3, "price"), (4, "pw_delta"), (5, "pw_rho")):
+        m, se = oracle.mean_se(rec[:, k])
+        assert r[name][0] == pytest.approx(m, rel=1e-9), name
+        assert r[name][1] == pytest.approx(se, rel=1e-6), name
+
+
+def test_european_price_against_characteristic_function(hm, ctx):
+    """Exact simulation has no discretisation bias: 2^17 paths, one step."""
+    opts = hm.Options(scheme=hm.EXACT, greeks=hm.GREEKS_PATHWISE)
+    for p in (PB, PB.replace(K=80.0)):
+        r = ctx.price_greeks(p.__dict__, oracle.EURO_CALL, 1 << 17, 1, 21, opts)
+        assert abs(r["price"][0] - analytic.heston_call(p)) < 4 * r["price"][1]
+
+
+def test_paper_exact_simulation_asian_value(hm, ctx):
+    """Paper parameters, fixings at 0.25, 0.5, 0.75, 1: the paper's
+    exact-simulation value 4.3840 (0.0064)."""
+    opts = hm.Options(scheme=hm.EXACT, greeks=hm.GREEKS_PATHWISE)
+    r = ctx.price_greeks(PP.__dict__, oracle.ASIAN_CALL, 1 << 17, 4, 23, opts)
+    assert abs(r["price"][0] - 4.3840) < 3 * math.hypot(r["price"][1], 0.0064)
+
+
+def test_rejections(hm, ctx):
+    import torch
+    E = hm.EXACT
+    cases = [
+        (PB, hm.Options(scheme=E, precision=hm.FP32, greeks=hm.GREEKS_PATHWISE), 4, -5),
+        (PB, hm.Options(scheme=E, rng=hm.SOBOL_BRIDGE, qmc_replicates=2,
+                        greeks=hm.GREEKS_PATHWISE), 4, -5),
+        (PB, hm.Options(scheme=E), 4, -5),  # default greeks include the fused bumps
+        (PB.replace(sigma=0.0), hm.Options(scheme=E, greeks=hm.GREEKS_PATHWISE), 4, -1),
+        (PB, hm.Options(scheme=E, greeks=hm.GREEKS_PATHWISE), hm.EXACT_MAX_STEPS + 1, -5),
+    ]
+    for p, o, N, status in cases:
+        with pytest.raises(hm.HestonError) as e:
+            ctx.price_greeks(p.__dict__, oracle.EURO_CALL, 256, N, 1, o)
+        assert e.value.status == status
+    o = hm.Options(scheme=E, greeks=hm.GREEKS_PATHWISE)
+    ck = torch.empty(hm.ckpt_bytes(256, 8, 8, hm.FP64), dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(hm.HestonError) as e:
+        ctx.adjoint_forward(PB.__dict__, 0, 256, 8, 1, ck, 8, o)
+    assert e.value.status == -5
+    with pytest.raises(hm.HestonError) as e:
+        ctx.price_batch([dict(params=PB.__dict__, type=0, n_steps=4, n_paths=100, seed=1,
+                              want=1)], o)
+    assert e.value.status == -5
