@@ -11,7 +11,7 @@ Prints ONE JSON line (rank 0).  Also reported: the roofline of the path kernel
 (an operation count per path-step against the FP32 vector peak), the Sobol +
 Brownian-bridge variant of the same step, the same step under the
 quadratic-exponential scheme, the same step with the geometric-average control
-variate, the adjoint against plain bump-and-revalue, the 4096-option batch,
+variate, exact (Broadie-Kaya) simulation, the adjoint against plain bump-and-revalue, the 4096-option batch,
 the serving loop's latency, and the
 CPU oracle timed on a bounded sample of the same workload.
 """
@@ -50,7 +50,7 @@ ALU_PEAK_OPS = 256 * 128 * 2.4e9
 # a 256 MiB device copy reads under the same counters); see
 # profiles/price_kernel_asian_2p20x252_fp32_bumps_hbm_counters.md.  Set to None
 # whenever the kernel changes until the counters are taken again.
-TRAFFIC_BYTES_PER_LAUNCH = 836_229
+TRAFFIC_BYTES_PER_LAUNCH = 837_240
 
 
 def parse():
@@ -60,8 +60,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="qmc,qe,cv,adjoint,batch,serve",
-                    help="extra legs reported after the timed steps: qmc, qe, cv, adjoint, batch, serve, "
+    ap.add_argument("--legs", default="qmc,qe,cv,exact,adjoint,batch,serve",
+                    help="extra legs reported after the timed steps: qmc, qe, cv, exact, adjoint, batch, "
+                         "serve, "
                          "and copy (a 256 MiB device copy that calibrates HBM byte counters)")
     return ap.parse_args()
 
@@ -97,6 +98,26 @@ def cpu_baseline(target_s: float):
 
 ADJ_BUMPS = (("S0", 0, 1, 0.01), ("v0", 4, 1, 0.01), ("r", 2, 0, 1e-4), ("kappa", 5, 1, 0.01),
              ("theta", 6, 1, 0.01), ("sigma", 7, 1, 0.01), ("rho", 8, 0, 0.01))
+
+
+def exact_simulation(ctx, hm, torch):
+    """Exact (Broadie-Kaya) simulation, FP64: the European call in one step and
+    the paper's quarterly Asian call (paper parameters, four steps), 2^20 paths
+    each; price against the characteristic-function price (European)."""
+    from workloads import PAPER
+    out = {}
+    opts = hm.Options(scheme=hm.EXACT, greeks=hm.GREEKS_PATHWISE)
+    for name, params, opt, N in (("euro_call_1_step", BASE, hm.EURO_CALL, 1),
+                                 ("paper_asian_call_4_steps", PAPER, hm.ASIAN_CALL, 4)):
+        n = 1 << 20
+        ctx.price_greeks(params, opt, 1 << 16, N, 1, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.price_greeks(params, opt, n, N, 42, opts)
+        wall = time.perf_counter() - t0
+        out[name] = {"paths_per_s": n / wall, "path_steps_per_s": n * N / wall,
+                     "ms": wall * 1e3, "kernel_ms": r["device_ms"], "price": r["price"]}
+    return out
 
 
 def adjoint_vs_bump(ctx, hm, torch):
@@ -327,6 +348,8 @@ def main():
             "kernel_ms": float(np.mean(ck)), "price": rc["price"], "cv_price": rc["cv_price"],
             "cv_beta": rc["cv_beta"], "cv_mean": rc["cv_mean"], "variance_reduction": vrf,
             "equal_se_path_steps_per_s": path_steps / (c_ms * 1e-3) * vrf}
+    if "exact" in legs:
+        out["exact_simulation"] = exact_simulation(ctx, hm, torch)
     if "adjoint" in legs:
         out["adjoint_vs_bump"] = adjoint_vs_bump(ctx, hm, torch)
     if "batch" in legs:
