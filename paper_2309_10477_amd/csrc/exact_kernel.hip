@@ -50,11 +50,10 @@ namespace heston {
 namespace {
 
 constexpr double PI = 3.14159265358979323846;
-constexpr double TWO_PI = 6.28318530717958647693;
 constexpr double GRID_EPS = 1e-10;
 
+// Philox blocks of one (path, step).
 struct Draw {
-    const ExactLaunch *L;
     uint32_t plo, phi, step, k0, k1;
     __device__ U4 block(uint32_t k) const
     {
@@ -269,7 +268,7 @@ __global__ __launch_bounds__(BLOCK) void exact_kernel(const ExactLaunch L)
         double *col = L.scratch + lane;
         for (uint64_t i = lane; i < L.n_paths; i += L.n_lanes) {
             const uint64_t p = L.first_path + i;
-            Draw dr{&L, (uint32_t)p, (uint32_t)(p >> 32), 0u, (uint32_t)L.seed,
+            Draw dr{(uint32_t)p, (uint32_t)(p >> 32), 0u, (uint32_t)L.seed,
                     (uint32_t)(L.seed >> 32)};
             double x = 0.0, V = L.v0, A = 0.0, B = 0.0, Itot = 0.0;
             bool bad = false;
