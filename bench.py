@@ -50,14 +50,14 @@ ALU_PEAK_OPS = 256 * 128 * 2.4e9
 # a 256 MiB device copy reads under the same counters); see
 # profiles/price_kernel_asian_2p20x252_fp32_bumps_hbm_counters.md.  Set to None
 # whenever the kernel changes until the counters are taken again.
-TRAFFIC_BYTES_PER_LAUNCH = 837_240
+TRAFFIC_BYTES_PER_LAUNCH = 837_241
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--legs", default="qmc,qe,cv,exact,adjoint,batch,serve",
