@@ -77,9 +77,10 @@ __device__ __forceinline__ void box_muller(double ua, double ub, double &za, dou
 // Single precision: Wichura's algorithm AS 241 (Applied Statistics 37, 1988),
 // its single-precision form PPND7 (relative accuracy about 1e-7), evaluated
 // branch-free: the central rational in r = 0.180625 - q^2, q = u - 1/2, for
-// u >= 0.075 and the first tail rational in t = sqrt(-ln u) - 1.6 below, both
-// computed and one selected.  All coefficients are positive and r, t >= 0 on
-// their ranges, so neither polynomial cancels in binary32.  The second tail
+// u >= 0.075 and the first tail rational in t = sqrt(-ln u) - 1.6 below: both
+// polynomials computed, numerator and denominator selected, one reciprocal.
+// All coefficients are positive and r, t >= 0 on their ranges, so neither
+// polynomial cancels in binary32.  The second tail
 // (sqrt(-ln u) > 5, u < 1.4e-11) lies outside the stated domain.
 // Double precision: the device math library's normcdfinv.
 __device__ __forceinline__ float inv_normal_lower(float u)
@@ -87,14 +88,14 @@ __device__ __forceinline__ float inv_normal_lower(float u)
     const float q = u - 0.5f, r = 0.180625f - q * q;
     const float num_c = ((59.109374720f * r + 159.29113202f) * r + 50.434271938f) * r + 3.3871327179f;
     const float den_c = ((67.187563600f * r + 78.757757664f) * r + 17.895169469f) * r + 1.0f;
-    const float zc = q * num_c * __builtin_amdgcn_rcpf(den_c);
     // -ln u = -ln2 log2 u
     const float t =
         __builtin_amdgcn_sqrtf(-0.69314718055994530942f * __builtin_amdgcn_logf(u)) - 1.6f;
     const float num_t = ((0.17023821103f * t + 1.3067284816f) * t + 2.7568153900f) * t + 1.4234372777f;
     const float den_t = (0.12021132975f * t + 0.73700164250f) * t + 1.0f;
-    const float zt = -num_t * __builtin_amdgcn_rcpf(den_t);
-    return u < 0.075f ? zt : zc;
+    // one reciprocal, of the selected denominator
+    const bool tail = u < 0.075f;
+    return (tail ? -num_t : q * num_c) * __builtin_amdgcn_rcpf(tail ? den_t : den_c);
 }
 __device__ __forceinline__ double inv_normal_lower(double u) { return normcdfinv(u); }
 
