@@ -597,34 +597,33 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
 }
 
 // Sums the partial records (W doubles each) of each replicate in a fixed order.
+// Thread t of the block owns column t % W of row group t / W: it adds rows
+// g, g + G, g + 2G, ... (G = RB / W groups), so consecutive threads read
+// consecutive doubles; the G group sums of each column are then added in
+// group order.
+constexpr int RB = 1024; // threads of the reduction block
 template <int W>
-__global__ __launch_bounds__(BLOCK) void reduce_partials(const double *__restrict__ partials,
-                                                         uint32_t blocks_per_rep,
-                                                         double *__restrict__ rep_sums)
+__global__ __launch_bounds__(RB) void reduce_partials(const double *__restrict__ partials,
+                                                      uint32_t blocks_per_rep,
+                                                      double *__restrict__ rep_sums)
 {
-    __shared__ double red[BLOCK][W + 1];
+    constexpr int G = RB / W;
+    __shared__ double red[G][W];
     const double *base = partials + (uint64_t)blockIdx.x * blocks_per_rep * W;
-    double acc[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k)
-        acc[k] = 0.0;
-    for (uint32_t b = threadIdx.x; b < blocks_per_rep; b += BLOCK)
-#pragma unroll
-        for (int k = 0; k < W; ++k)
-            acc[k] += base[(uint64_t)b * W + k];
-#pragma unroll
-    for (int k = 0; k < W; ++k)
-        red[threadIdx.x][k] = acc[k];
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < (unsigned)s)
-#pragma unroll
-            for (int k = 0; k < W; ++k)
-                red[threadIdx.x][k] += red[threadIdx.x + s][k];
-        __syncthreads();
+    const int t = threadIdx.x, col = t % W, grp = t / W;
+    if (grp < G) {
+        double acc = 0.0;
+        for (uint32_t b = grp; b < blocks_per_rep; b += G)
+            acc += base[(uint64_t)b * W + col];
+        red[grp][col] = acc;
     }
-    if (threadIdx.x < W)
-        rep_sums[(uint64_t)blockIdx.x * W + threadIdx.x] = red[0][threadIdx.x];
+    __syncthreads();
+    if (t < W) {
+        double s = 0.0;
+        for (int g = 0; g < G; ++g)
+            s += red[g][t];
+        rep_sums[(uint64_t)blockIdx.x * W + t] = s;
+    }
 }
 
 // Plain bump-and-revalue: per-path central differences of stored payoff rows.
@@ -859,10 +858,10 @@ hipError_t launch_reduce_rows(const double *partials, uint32_t rows, uint32_t w,
 hipError_t launch_reduce(const PriceLaunch &L, double *rep_sums, hipStream_t stream)
 {
     if (L.cv)
-        hipLaunchKernelGGL(reduce_partials<N_ACC_CV>, dim3(L.n_reps), dim3(BLOCK), 0, stream,
+        hipLaunchKernelGGL(reduce_partials<N_ACC_CV>, dim3(L.n_reps), dim3(RB), 0, stream,
                            L.partials, L.blocks_per_rep, rep_sums);
     else
-        hipLaunchKernelGGL(reduce_partials<N_ACC>, dim3(L.n_reps), dim3(BLOCK), 0, stream,
+        hipLaunchKernelGGL(reduce_partials<N_ACC>, dim3(L.n_reps), dim3(RB), 0, stream,
                            L.partials, L.blocks_per_rep, rep_sums);
     return hipGetLastError();
 }
