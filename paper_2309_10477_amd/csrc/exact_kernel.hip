@@ -113,9 +113,15 @@ __device__ Cx bessel_sum(Cx z, double nu, bool &bad)
     const Cx q = z * z * 0.25;
     Cx t{1.0, 0.0}, s{1.0, 0.0};
     for (int k = 1; k < 2000; ++k) {
-        t = t * q * (1.0 / ((double)k * ((double)k + nu)));
+        // 1 / (k (k + nu)): hardware reciprocal and one Newton step
+        const double den = (double)k * ((double)k + nu);
+        double rc = __builtin_amdgcn_rcp(den);
+        rc = rc * fma(-den, rc, 2.0);
+        t = t * q * rc;
         s = s + t;
-        if ((double)k > 0.5 * az && cabs(t) < 1e-17 * cabs(s))
+        // |t| < 1e-17 |s|, compared squared
+        if ((double)k > 0.5 * az &&
+            t.re * t.re + t.im * t.im < 1e-34 * (s.re * s.re + s.im * s.im))
             return s;
     }
     bad = true;
