@@ -204,3 +204,24 @@ def test_rejections(hm, ctx):
         ctx.price_batch([dict(params=PB.__dict__, type=hm.ASIAN_CALL, n_steps=4, n_paths=100,
                               seed=1, want=1)], cv)
     assert e.value.status == -5
+
+
+def test_full_size_sampled_paths_and_estimate(hm, ctx):
+    """The benchmark's control-variate step (2^20 x 252, FP32, fused bumps), in
+    the launch it times: sampled paths' arithmetic and control payoffs against
+    the oracle, and beta and the estimate against oracle.control_variate on
+    every dumped path (the kernel's FP32 payoffs, so the host arithmetic alone
+    is compared) with the device control mean."""
+    n, N, seed = 1 << 20, 252, 42
+    opts = hm.Options(precision=hm.FP32, control_variate=hm.CONTROL_GEOMETRIC)
+    r = ctx.price_greeks(PB.__dict__, hm.ASIAN_CALL, n, N, seed, opts)
+    full = ctx.dump_paths(PB.__dict__, hm.ASIAN_CALL, n, N, seed, 0, n, opts).cpu().numpy()
+    for first in (0, n // 2 + 4321, n - 300):
+        a = oracle.simulate(PB, oracle.ASIAN_CALL, N, seed, first, 300, threads=8)[:, 3]
+        g = oracle.simulate(PB, oracle.GEO_ASIAN_CALL, N, seed, first, 300, threads=8)[:, 3]
+        close("pay", full[first:first + 300, 3], a, TOL[1], PB.S0)
+        close("geo pay", full[first:first + 300, 15], g, TOL[1], PB.S0)
+    est, se, beta = oracle.control_variate(full[:, 3], full[:, 15], r["cv_mean"])
+    assert r["cv_beta"] == pytest.approx(beta, rel=1e-9)
+    assert r["cv_price"][0] == pytest.approx(est, rel=1e-10)
+    assert r["cv_price"][1] == pytest.approx(se, rel=1e-6)

@@ -141,3 +141,22 @@ def test_rejections(hm, ctx):
         ctx.price_batch([dict(params=PB.__dict__, type=0, n_steps=4, n_paths=100, seed=1,
                               want=1)], o)
     assert e.value.status == -5
+
+
+def test_full_size_sampled_paths(hm, ctx):
+    """The benchmark's exact European leg (2^20 paths, one step), in the launch it
+    times: sampled paths against the oracle, and the reduced estimates against
+    the host sums of every dumped path."""
+    n, seed = 1 << 20, 42
+    opts = hm.Options(scheme=hm.EXACT, greeks=hm.GREEKS_PATHWISE)
+    r = ctx.price_greeks(PB.__dict__, oracle.EURO_CALL, n, 1, seed, opts)
+    full = ctx.dump_paths(PB.__dict__, oracle.EURO_CALL, n, 1, seed, 0, n, opts).cpu().numpy()
+    for first in (0, n // 2 + 777, n - 200):
+        rec, I = bk.simulate_counter(PB, oracle.EURO_CALL, 1, seed, first, 200, integral=True)
+        close("S_T", full[first:first + 200, 0], rec[:, 0], PB.S0)
+        close("pay", full[first:first + 200, 3], rec[:, 3], PB.S0)
+        close("int V", full[first:first + 200, 15], I, PB.v0 * PB.T)
+    for k, name in ((3, "price"), (4, "pw_delta"), (5, "pw_rho")):
+        m, se = oracle.mean_se(full[:, k])
+        assert r[name][0] == pytest.approx(m, rel=1e-9), name
+        assert r[name][1] == pytest.approx(se, rel=1e-6), name
