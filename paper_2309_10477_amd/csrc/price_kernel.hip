@@ -208,10 +208,13 @@ __device__ __forceinline__ void qe_step(R &y, R &w, const QEGrid<R> &g, R z1l, R
     const R a = m * fast_rcp(R(1) + b2);
     const R bz = b + zv;
     const R wq = a * bz * bz;
-    // exponential branch: 1 - p = 2 / (psi + 1), 1 / beta = m (psi + 1) / 2
+    // exponential branch: p = (psi - 1) / (psi + 1), 1 - p = 2 / (psi + 1),
+    // 1 / beta = m (psi + 1) / 2; uv <= p is tested as uv (psi + 1) <= psi - 1
+    // and ln((1 - p) / (1 - uv)) as -ln((psi + 1)(1 - uv) / 2)
     const R pp1 = psi + R(1);
-    const R p = (psi - R(1)) * fast_rcp(pp1);
-    const R we = uv <= p ? R(0) : (R(0.5) * m * pp1) * fast_log(R(2) * fast_rcp(pp1 * (R(1) - uv)));
+    const R we = uv * pp1 <= psi - R(1)
+                     ? R(0)
+                     : -(R(0.5) * m * pp1) * fast_log(R(0.5) * pp1 * (R(1) - uv));
     const R wn = psi <= R(1.5) ? wq : we;
     y = y + g.k0 + g.k1 * w + g.k2 * wn + fast_sqrt(g.k3 * w + g.k4 * wn) * z1l;
     w = wn;
