@@ -235,11 +235,17 @@ heston_status heston_price_greeks(const heston_params *params, heston_option_typ
  * parity checks: writes count x HESTON_DUMP_WIDTH doubles, row-major, to the
  * DEVICE buffer `out_dev` (caller-owned, at least count*HESTON_DUMP_WIDTH*8
  * bytes).  The records are produced by the pricing kernel itself.  Columns:
- *   0 S_T, 1 V_T (carried variance), 2 Sbar (Asian average, S_T for European),
+ *   0 S_T, 1 V_T (carried variance), 2 Sbar (Asian average: arithmetic or
+ *     geometric by type; S_T for European),
  *   3 discounted payoff, 4 pathwise Delta, 5 pathwise Rho,
  *   6..13 discounted payoffs of the bumped scenarios S0+, S0-, v0+, v0-, r+,
  *         r-, T+, T- (NaN unless opts->greeks has BUMP_FUSED),
- *   14 ln(S_T/S0), 15 reserved (0).
+ *   14 ln(S_T/S0),
+ *   15 with HESTON_CONTROL_GEOMETRIC the discounted control payoff (geometric
+ *      average, same kind and strike); under HESTON_EXACT the integral of V
+ *      over [0, T]; otherwise 0.
+ * Under HESTON_EXACT a path outside the sampler's range has NaN in every
+ * column. 
  * For Sobol requests `first + count` must not exceed n_paths. */
 #define HESTON_DUMP_WIDTH 16
 heston_status heston_dump_paths(heston_ctx *ctx, const heston_params *params,

@@ -32,7 +32,7 @@ CONTROL_MAX_FIXINGS = 8192
 VALID_PRICE, VALID_PATHWISE, VALID_BUMPS, VALID_ADJOINT, VALID_CONTROL = 1, 2, 4, 8, 16
 DUMP_WIDTH = 16
 DUMP_FIELDS = ("S_T", "V_T", "Sbar", "pay", "pw_delta", "pw_rho", "pay_S0+", "pay_S0-",
-               "pay_v0+", "pay_v0-", "pay_r+", "pay_r-", "pay_T+", "pay_T-", "x_T", "reserved")
+               "pay_v0+", "pay_v0-", "pay_r+", "pay_r-", "pay_T+", "pay_T-", "x_T", "aux")
 STATUS = {0: "OK", 1: "PENDING", -1: "INVALID_ARGUMENT", -2: "OUT_OF_MEMORY",
           -3: "OVER_BUDGET", -4: "DEVICE_ERROR", -5: "UNSUPPORTED", -6: "NOT_FOUND"}
 PARAM_NAMES = ("S0", "K", "r", "T", "v0", "kappa", "theta", "sigma", "rho")
