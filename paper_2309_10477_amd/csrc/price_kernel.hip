@@ -602,23 +602,37 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
 // Sums the partial records (W doubles each) of each replicate in a fixed order.
 // Thread t of the block owns column t % W of row group t / W: it adds rows
 // g, g + G, g + 2G, ... (G = RB / W groups), so consecutive threads read
-// consecutive doubles; the G group sums of each column are then added in
-// group order.
+// consecutive doubles, into U running sums (row g + (U i + u) G into sum u),
+// so that U loads are in flight; the U sums, then the G group sums of each
+// column, are added in order.
 constexpr int RB = 1024; // threads of the reduction block
 template <int W>
 __global__ __launch_bounds__(RB) void reduce_partials(const double *__restrict__ partials,
                                                       uint32_t blocks_per_rep,
                                                       double *__restrict__ rep_sums)
 {
-    constexpr int G = RB / W;
+    constexpr int G = RB / W, U = 8;
     __shared__ double red[G][W];
     const double *base = partials + (uint64_t)blockIdx.x * blocks_per_rep * W;
     const int t = threadIdx.x, col = t % W, grp = t / W;
     if (grp < G) {
-        double acc = 0.0;
-        for (uint32_t b = grp; b < blocks_per_rep; b += G)
-            acc += base[(uint64_t)b * W + col];
-        red[grp][col] = acc;
+        double acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            acc[u] = 0.0;
+        for (uint32_t b = grp; b < blocks_per_rep; b += U * G) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t row = b + (uint32_t)(u * G);
+                if (row < blocks_per_rep)
+                    acc[u] += base[(uint64_t)row * W + col];
+            }
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            sum += acc[u];
+        red[grp][col] = sum;
     }
     __syncthreads();
     if (t < W) {
