@@ -23,7 +23,7 @@ SOURCES = ("api.hip", "price_kernel.hip", "adjoint_kernel.hip", "batch_kernel.hi
 SRC = [os.path.join(HERE, "csrc", f) for f in SOURCES]
 HDRS = [os.path.join(HERE, "csrc", f) for f in ("internal.hpp", "device_math.hpp", "cplx.hpp",
                                                 "path_step.hpp", "runtime.hpp",
-                                                "batch_plan.hpp")] + \
+                                                "batch_plan.hpp", "admission.hpp")] + \
     [os.path.join(os.path.dirname(HERE), "include", "heston.h")]
 LIB = os.path.join(HERE, "libheston.so")
 OBJ_DIR = os.path.join(HERE, "_build")

@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "../../include/heston.h"
+#include "admission.hpp"
 #include "batch_plan.hpp"
 #include "device_math.hpp"
 #include "internal.hpp"
@@ -141,69 +142,6 @@ using namespace heston::rt;
 using Clock = std::chrono::steady_clock;
 
 namespace {
-
-// First-fit allocator over one device buffer, in 256-byte units.
-class Pool {
-  public:
-    void init(unsigned char *base, uint64_t bytes)
-    {
-        base_ = base;
-        free_.clear();
-        if (bytes >= 256)
-            free_[0] = bytes & ~uint64_t(255);
-    }
-    uint64_t free_bytes() const
-    {
-        uint64_t t = 0;
-        for (auto &f : free_)
-            t += f.second;
-        return t;
-    }
-    unsigned char *alloc(uint64_t bytes)
-    {
-        bytes = (bytes + 255) & ~uint64_t(255);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                const uint64_t off = it->first, rest = it->second - bytes;
-                free_.erase(it);
-                if (rest)
-                    free_[off + bytes] = rest;
-                used_[off] = bytes;
-                return base_ + off;
-            }
-        }
-        return nullptr;
-    }
-    void release(unsigned char *p)
-    {
-        const uint64_t off = (uint64_t)(p - base_);
-        auto u = used_.find(off);
-        if (u == used_.end())
-            return;
-        uint64_t bytes = u->second;
-        used_.erase(u);
-        auto next = free_.lower_bound(off);
-        uint64_t start = off;
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                start = prev->first;
-                bytes += prev->second;
-                free_.erase(prev);
-            }
-        }
-        next = free_.find(off + (bytes - (off - start)));
-        if (next != free_.end()) {
-            bytes += next->second;
-            free_.erase(next);
-        }
-        free_[start] = bytes;
-    }
-
-  private:
-    unsigned char *base_ = nullptr;
-    std::map<uint64_t, uint64_t> free_, used_;
-};
 
 struct Req {
     heston_request r;
@@ -319,17 +257,10 @@ heston_status grow_launch(Launch &L, size_t n_opts, size_t n_items)
 // slot and pool memory are available.
 void admit(heston_server *s)
 {
-    while (!s->queue.empty() && s->active.size() < s->cfg.max_active) {
-        Req *q = s->queue.front();
-        const uint64_t bytes = sizeof(ReqState) + (uint64_t)q->cap_items * N_ACC * 8;
-        unsigned char *m = s->pool.alloc(bytes);
-        if (!m)
-            break;
-        q->mem = m;
-        s->queue.pop_front();
-        s->active.push_back(q);
-        s->stats.admitted++;
-    }
+    s->stats.admitted += admit_in_order(
+        s->queue, s->active, s->cfg.max_active, s->pool,
+        [](const Req *q) { return sizeof(ReqState) + (uint64_t)q->cap_items * N_ACC * 8; },
+        [](Req *q, unsigned char *m) { q->mem = m; });
 }
 
 // Items a request asks for in the next launch.
