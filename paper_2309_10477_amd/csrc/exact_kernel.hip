@@ -135,10 +135,11 @@ struct PhiCtx {
     double log_s_zk;           // ln S(z(0))
 };
 
-// log Phi(a).  ln z(a) is summed from its factors (ln r + ln 4g - g D/2 -
+// log Phi(a) = lp + ln S(z(a)) (lp returned, S(z(a)) in *s; S = 1 when r = 0).
+// ln z(a) is summed from its factors (ln r + ln 4g - g D/2 -
 // ln(sigma^2 (1 - e^{-gD}))): it cannot underflow, and its imaginary part is
 // an argument of z continuous along a >= 0, the branch of (z/2)^nu.
-__device__ Cx log_phi(const ExactLaunch &L, const PhiCtx &pc, double a, bool &bad)
+__device__ Cx log_phi_part(const ExactLaunch &L, const PhiCtx &pc, double a, Cx *s, bool &bad)
 {
     const Cx g = csqrt(Cx{L.kappa2, -L.two_sigma2 * a});
     const Cx eg = cexp(g * (-L.D));
@@ -149,12 +150,29 @@ __device__ Cx log_phi(const ExactLaunch &L, const PhiCtx &pc, double a, bool &ba
     const Cx t2 = (Cx{L.coth_k, 0.0} - g * (one + eg) / ome) * (pc.sum_v * L.inv_sigma2);
     // ln z(a) / r
     const Cx lz0 = lg - g * (0.5 * L.D) - lome + Cx{L.log4_over_sigma2, 0.0};
-    if (pc.r == 0.0) // I_nu(z) ~ (z/2)^nu / Gamma(nu+1) as z -> 0
+    if (pc.r == 0.0) { // I_nu(z) ~ (z/2)^nu / Gamma(nu+1) as z -> 0
+        *s = Cx{1.0, 0.0};
         return t1 + t2 + (lz0 - Cx{L.log_zk_scale, 0.0}) * L.nu;
+    }
     const Cx lz{lz0.re + log(pc.r), lz0.im};
-    const Cx s = bessel_sum(cexp(lz), L.nu, bad);
-    const Cx ls = clog(s);
-    return t1 + t2 + Cx{L.nu * (lz.re - pc.log_zk) + ls.re - pc.log_s_zk, L.nu * lz.im + ls.im};
+    *s = bessel_sum(cexp(lz), L.nu, bad);
+    return t1 + t2 + Cx{L.nu * (lz.re - pc.log_zk) - pc.log_s_zk, L.nu * lz.im};
+}
+
+// log Phi(a), for the moments at small a.
+__device__ Cx log_phi(const ExactLaunch &L, const PhiCtx &pc, double a, bool &bad)
+{
+    Cx s;
+    const Cx lp = log_phi_part(L, pc, a, &s, bad);
+    return lp + clog(s);
+}
+
+// Phi(a) on the grid: the Bessel sum multiplies instead of entering a logarithm.
+__device__ Cx phi(const ExactLaunch &L, const PhiCtx &pc, double a, bool &bad)
+{
+    Cx s;
+    const Cx lp = log_phi_part(L, pc, a, &s, bad);
+    return cexp(lp) * s;
 }
 
 // Conditional mean and standard deviation of I from log Phi at a = h, 2h.
@@ -221,7 +239,7 @@ __device__ double sample_integral(const ExactLaunch &L, double vu, double vt, do
     for (;;) {
         double last = 0.0;
         for (; j < J; ++j) {
-            const Cx ph = cexp(log_phi(L, pc, h * (double)(j + 1), bad));
+            const Cx ph = phi(L, pc, h * (double)(j + 1), bad);
             col[(size_t)j * L.n_lanes] = ph.re;
             last = cabs(ph);
             if (last / (double)(j + 1) >= thr)
