@@ -754,7 +754,7 @@ static heston_status geo_control_setup(heston_ctx *c, const Request &q, GeoContr
     // average of a Brownian motion of variance rate min(v0, theta) (the slower
     // decay of the two levels) has decayed, exp(-v^2 s^2 / 2) = e^-39, times 3
     // for the heavier tails of the Heston transform; a power of two in [64,
-    // GEO_MAX_FIXED_PANELS].  If the transform has not decayed there, the
+    // GEO_MAX_FIXED_RANGE].  If the transform has not decayed there, the
     // device search takes over.
     {
         const uint32_t n = g.n_fix;
@@ -766,10 +766,10 @@ static heston_status geo_control_setup(heston_ctx *c, const Request &q, GeoContr
                                                         : std::max(p.v0, p.theta);
         const double s2 = vmin * mm / ((double)n * n);
         const double v = s2 > 0 ? 3.0 * std::sqrt(78.0 / s2) : 1e300;
-        uint32_t panels = 64;
-        while (panels < GEO_MAX_FIXED_PANELS && panels < v)
-            panels *= 2;
-        g.n_panels = panels;
+        uint32_t range = 64;
+        while (range < GEO_MAX_FIXED_RANGE && range < v)
+            range *= 2;
+        g.v_max = range;
     }
     static const struct Rule {
         double x[8], w[8];

@@ -13,12 +13,12 @@
 //   A(tau) = A0 + r a tau + kappa theta (r_- tau - ln((1 - g e^{-d tau})/(1 - g)) / c2).
 // The call price is e^{-rT} ((E[G] - K)/2 + (1/pi) int_0^inf Re[e^{-iv ln K}
 // (M(1+iv) - K M(iv)) / (iv)] dv) (Gil-Pelaez), integrated by 16-point
-// Gauss-Legendre on unit panels up to the first power of two where the
-// integrand's modulus bound falls below 1e-15 (E[G] + K).
+// Gauss-Legendre on panels of width GEO_PANEL_WIDTH up to a power of two v_max
+// where the integrand's modulus bound is below 1e-15 (E[G] + K).
 //
 // Each thread evaluates one transform (a sequential pass over the fixing
 // dates), so a launch is bound by that chain's latency, not by throughput.
-// The first pass integrates over [0, g.n_panels] (a range the host sizes from
+// The first pass integrates over [0, g.v_max] (a range the host sizes from
 // the variance of ln G) in one node launch that also evaluates the bound at
 // its end; only if that bound is not small does the caller run the search: a bound kernel (one wave) at v =
 // 2^k, then nodes up to the first 2^k whose bound is small (a fixed grid whose
@@ -35,10 +35,15 @@
 namespace heston {
 namespace {
 
-constexpr int GEO_MAX_LOG2_PANELS = 14; // v_max <= 2^14
-static_assert(GEO_MAX_LOG2_PANELS < GEO_BOUND_POINTS, "bound table too short");
+constexpr int GEO_MAX_LOG2_RANGE = 14; // v_max <= 2^14
+// Panel width: the integrand varies on the scale of 1 / sd(ln G) and is
+// analytic in a strip about the real axis, so 16 nodes per 4 units resolve
+// it to rounding (checked against adaptive quadrature: 1e-13 relative up to
+// width 8 on the tested parameter sets).
+constexpr uint32_t GEO_PANEL_WIDTH = 4;
+static_assert(GEO_MAX_LOG2_RANGE < GEO_BOUND_POINTS, "bound table too short");
 static_assert(2 * GEO_BOUND_POINTS < 64, "one wave evaluates every bound and E[G]");
-constexpr uint32_t GEO_NODE_THREADS = 32u << GEO_MAX_LOG2_PANELS; // 16 nodes x 2 transforms
+constexpr uint32_t GEO_NODE_THREADS = 32u << GEO_MAX_LOG2_RANGE; // 16 nodes x 2 transforms
 constexpr uint32_t GEO_NODE_BLOCKS = GEO_NODE_THREADS / BLOCK;
 constexpr double GEO_TOL = 1e-15;
 
@@ -109,27 +114,29 @@ __global__ __launch_bounds__(64) void geo_bound_kernel(const GeoControl g, doubl
         out[2] = exp(log_transform(g, Cx{1.0, 0.0}).re); // E[G]
 }
 
-// Panels of the integral: the first 2^k (k <= GEO_MAX_LOG2_PANELS) whose bound
+// Range of the integral: the first 2^k (k <= GEO_MAX_LOG2_RANGE) whose bound
 // is below tolerance, or 0 if none is.
-__device__ uint32_t panels_from(const double *bound, double EG, double K)
+__device__ uint32_t range_from(const double *bound, double EG, double K)
 {
     const double tol = GEO_TOL * (EG + K);
-    for (int k = 0; k <= GEO_MAX_LOG2_PANELS; ++k)
+    for (int k = 0; k <= GEO_MAX_LOG2_RANGE; ++k)
         if (bound[2 * k] + bound[2 * k + 1] <= tol)
             return 1u << k;
     return 0u;
 }
 
-// Gauss-Legendre nodes of the integral, two transforms per node.  With
-// `fixed` panels the three threads after the nodes evaluate the modulus bound
-// at v = fixed (out[4], out[5]) and E[G] (out[2]); otherwise the panel count
-// comes from the bound table of geo_bound_kernel.
+// Gauss-Legendre nodes of the integral over [0, range], two transforms per
+// node.  With a `fixed` range the three threads after the nodes evaluate the
+// modulus bound at v = fixed (out[4], out[5]) and E[G] (out[2]); otherwise the
+// range comes from the bound table of geo_bound_kernel.
 __global__ __launch_bounds__(BLOCK) void geo_node_kernel(const GeoControl g, uint32_t fixed,
                                                          const double *bound, double *out,
                                                          double *partials)
 {
     __shared__ double red[BLOCK / 64];
-    const uint32_t panels = fixed ? fixed : panels_from(bound, out[2], g.K);
+    const uint32_t range = fixed ? fixed : range_from(bound, out[2], g.K);
+    const uint32_t width = range < GEO_PANEL_WIDTH ? range : GEO_PANEL_WIDTH;
+    const uint32_t panels = width ? range / width : 0u;
     const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
     const uint32_t n_node_threads = 32u * panels;
     double val = 0.0;
@@ -137,8 +144,8 @@ __global__ __launch_bounds__(BLOCK) void geo_node_kernel(const GeoControl g, uin
         const uint32_t node = t >> 1, panel = node >> 4, j = node & 15;
         const double x = j < 8 ? -g.gl_x[7 - j] : g.gl_x[j - 8];
         const double w = j < 8 ? g.gl_w[7 - j] : g.gl_w[j - 8];
-        const double v = (double)panel + 0.5 + 0.5 * x;
-        val = 0.5 * w * integrand_part(g, v, (int)(t & 1));
+        const double v = ((double)panel + 0.5 + 0.5 * x) * (double)width;
+        val = 0.5 * (double)width * w * integrand_part(g, v, (int)(t & 1));
     } else if (fixed && t < n_node_threads + 2) {
         out[4 + (t - n_node_threads)] = bound_part(g, (double)fixed, (int)(t - n_node_threads));
     } else if (fixed && t == n_node_threads + 2) {
@@ -176,7 +183,7 @@ __global__ __launch_bounds__(BLOCK) void geo_finish_kernel(const GeoControl g, u
         const double EG = out[2], I = red[0];
         const double D = exp(-g.r * g.T);
         const bool ok = fixed ? out[4] + out[5] <= GEO_TOL * (EG + g.K)
-                              : panels_from(bound, EG, g.K) != 0u;
+                              : range_from(bound, EG, g.K) != 0u;
         const double call = D * (0.5 * (EG - g.K) + I / M_PI);
         const double nan = __builtin_nan("");
         out[0] = ok ? call : nan;
@@ -192,14 +199,14 @@ uint32_t geo_node_blocks() { return GEO_NODE_BLOCKS; }
 hipError_t launch_geo_price_fixed(const GeoControl &g, double *partials, double *buf,
                                   hipStream_t stream)
 {
-    static_assert((32u * GEO_MAX_FIXED_PANELS + 3u + BLOCK - 1) / BLOCK <= GEO_NODE_BLOCKS,
+    static_assert((32u * GEO_MAX_FIXED_RANGE + 3u + BLOCK - 1) / BLOCK <= GEO_NODE_BLOCKS,
                   "fixed range within the partials buffer");
-    if (g.n_panels < 1 || g.n_panels > GEO_MAX_FIXED_PANELS)
+    if (g.v_max < GEO_PANEL_WIDTH || g.v_max > GEO_MAX_FIXED_RANGE || g.v_max % GEO_PANEL_WIDTH)
         return hipErrorInvalidValue;
-    const uint32_t blocks = (32u * g.n_panels + 3u + BLOCK - 1) / BLOCK;
-    hipLaunchKernelGGL(geo_node_kernel, dim3(blocks), dim3(BLOCK), 0, stream, g, g.n_panels,
+    const uint32_t blocks = (32u * (g.v_max / GEO_PANEL_WIDTH) + 3u + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(geo_node_kernel, dim3(blocks), dim3(BLOCK), 0, stream, g, g.v_max,
                        (const double *)buf, buf + GEO_OUT, partials);
-    hipLaunchKernelGGL(geo_finish_kernel, dim3(1), dim3(BLOCK), 0, stream, g, g.n_panels, blocks,
+    hipLaunchKernelGGL(geo_finish_kernel, dim3(1), dim3(BLOCK), 0, stream, g, g.v_max, blocks,
                        (const double *)buf, (const double *)partials, buf + GEO_OUT);
     return hipGetLastError();
 }

@@ -138,7 +138,7 @@ struct GeoControl {
     double dt;                 // fixing time of step k is k dt
     const uint32_t *steps;     // fixing steps (device), or null = every step 1..n_fix
     uint32_t n_fix;
-    uint32_t n_panels;         // first range: unit Gauss-Legendre panels on [0, n_panels]
+    uint32_t v_max;            // first integration range [0, v_max] (a power of two)
     double gl_x[8], gl_w[8];   // positive 16-point Gauss-Legendre nodes and weights
 };
 
@@ -240,13 +240,13 @@ hipError_t launch_reduce(const PriceLaunch &L, double *rep_sums, hipStream_t str
 // at v = 2^k (M the transform of ln G; search only), then at GEO_OUT the
 // discounted call and put prices of G, E[G], the Gil-Pelaez integral and the
 // two bounds at the end of the fixed range.  The prices are NaN when the
-// transform has not decayed by the end of the range (fixed: g.n_panels, at
-// most GEO_MAX_FIXED_PANELS; search: 2^14).  `partials` (device [geo_node_blocks()]) holds one double per
-// block of the node kernel.
+// transform has not decayed by the end of the range (fixed: g.v_max, at most
+// GEO_MAX_FIXED_RANGE; search: 2^14).  `partials` (device [geo_node_blocks()])
+// holds one double per block of the node kernel.
 constexpr int GEO_BOUND_POINTS = 15;
 constexpr int GEO_OUT = 2 * GEO_BOUND_POINTS;
 constexpr int GEO_BUF_DOUBLES = GEO_OUT + 6;
-constexpr uint32_t GEO_MAX_FIXED_PANELS = 4096;
+constexpr uint32_t GEO_MAX_FIXED_RANGE = 4096;
 uint32_t geo_node_blocks();
 hipError_t launch_geo_price_fixed(const GeoControl &g, double *partials, double *buf,
                                   hipStream_t stream);
