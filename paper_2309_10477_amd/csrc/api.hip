@@ -434,10 +434,14 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
         return fail(HESTON_UNSUPPORTED, "too many paths for one launch");
     heston_status st;
     const size_t W = (size_t)L.acc_width();
+    const size_t chunks = (L.blocks_per_rep + REDUCE_CHUNK - 1) / REDUCE_CHUNK; // first level
     if ((st = reserve(c, c->partials, (size_t)L.n_reps * L.blocks_per_rep * W * 8)) != HESTON_OK ||
-        (st = reserve(c, c->rep_sums, (size_t)L.n_reps * W * 8)) != HESTON_OK)
+        (st = reserve(c, c->rep_sums, (size_t)L.n_reps * W * 8)) != HESTON_OK ||
+        (chunks > 1 &&
+         (st = reserve(c, c->reduce_tmp, (size_t)L.n_reps * chunks * W * 8)) != HESTON_OK))
         return st;
     L.partials = (double *)c->partials.ptr;
+    L.reduce_tmp = chunks > 1 ? (double *)c->reduce_tmp.ptr : nullptr;
     if (c->host_sums_bytes < (size_t)L.n_reps * W * 8) {
         if (c->host_sums)
             (void)hipHostFree(c->host_sums);
@@ -679,6 +683,7 @@ heston_status heston_ctx_destroy(heston_ctx *c)
     for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift, &c->sobol_hi, &c->sobol_perm, &c->sobol_dir12,
                       &c->bridge_start, &c->bridge_ops, &c->pay, &c->bump_partials,
                       &c->geo_buf, &c->geo_partials, &c->geo_steps, &c->exact_scratch,
+                      &c->reduce_tmp,
                       &c->bump_sums, &c->step_w, &c->batch_opts, &c->batch_items, &c->batch_partials,
                       &c->batch_sums, &c->batch_counter, &c->batch_scratch})
         if (b->ptr)

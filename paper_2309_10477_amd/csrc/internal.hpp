@@ -20,6 +20,8 @@ enum Estimator : int {
     N_EST
 };
 constexpr int N_ACC = 2 * N_EST;   // doubles per partial record
+// Records per block of the first level of a long reduction.
+constexpr uint32_t REDUCE_CHUNK = 256;
 // The arithmetic-Asian kernel with the geometric control adds two estimators:
 // the geometric payoff g and the difference a - g of the two payoffs.
 enum : int { EST_CV_GEO = N_EST, EST_CV_DIFF, N_EST_CV };
@@ -89,6 +91,9 @@ struct PriceLaunch {
     int bridge_depth;
     // outputs
     double *partials;               // device [n_reps][blocks_per_rep][acc_width()]
+    double *reduce_tmp;             // device [n_reps][ceil(blocks_per_rep / REDUCE_CHUNK)]
+                                    // [acc_width()] first-level sums, or null when
+                                    // blocks_per_rep <= REDUCE_CHUNK
     uint32_t blocks_per_rep;
     double *dump;                   // device [n_paths][DUMP_WIDTH] or null
     double *pay_out;                // device [n_paths] discounted payoff per path, or null

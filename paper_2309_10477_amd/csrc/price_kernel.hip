@@ -599,32 +599,37 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
     }
 }
 
-// Sums the partial records (W doubles each) of each replicate in a fixed order.
-// Thread t of the block owns column t % W of row group t / W: it adds rows
-// g, g + G, g + 2G, ... (G = RB / W groups), so consecutive threads read
-// consecutive doubles, into U running sums (row g + (U i + u) G into sum u),
-// so that U loads are in flight; the U sums, then the G group sums of each
-// column, are added in order.
-constexpr int RB = 1024; // threads of the reduction block
+// Sums runs of partial records (W doubles each) in a fixed order.  Block
+// (x, y) adds records [x chunk, min((x + 1) chunk, rep_rows)) of replicate y
+// (records y rep_rows + ...) into out[(y gridDim.x + x) W + ...].  Thread t
+// owns column t % W of row group t / W: it adds rows g, g + G, g + 2G, ...
+// (G = RB / W groups), so consecutive threads read consecutive doubles, into
+// U running sums (row g + (U i + u) G into sum u); the U sums, then the G
+// group sums of each column, are added in order.  One workgroup reads at a
+// few tens of GB/s, so long replicates are first cut into chunks of
+// REDUCE_CHUNK records, one block each, and the chunk sums reduced again.
+constexpr int RB = 1024; // threads of a reduction block
 template <int W>
-__global__ __launch_bounds__(RB) void reduce_partials(const double *__restrict__ partials,
-                                                      uint32_t blocks_per_rep,
-                                                      double *__restrict__ rep_sums)
+__global__ __launch_bounds__(RB) void reduce_partials(const double *__restrict__ in,
+                                                      uint32_t rep_rows, uint32_t chunk,
+                                                      double *__restrict__ out)
 {
     constexpr int G = RB / W, U = 8;
     __shared__ double red[G][W];
-    const double *base = partials + (uint64_t)blockIdx.x * blocks_per_rep * W;
+    const uint32_t first = blockIdx.x * chunk;
+    const uint32_t rows = rep_rows - first < chunk ? rep_rows - first : chunk;
+    const double *base = in + ((uint64_t)blockIdx.y * rep_rows + first) * W;
     const int t = threadIdx.x, col = t % W, grp = t / W;
     if (grp < G) {
         double acc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
             acc[u] = 0.0;
-        for (uint32_t b = grp; b < blocks_per_rep; b += U * G) {
+        for (uint32_t b = grp; b < rows; b += U * G) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t row = b + (uint32_t)(u * G);
-                if (row < blocks_per_rep)
+                if (row < rows)
                     acc[u] += base[(uint64_t)row * W + col];
             }
         }
@@ -639,8 +644,26 @@ __global__ __launch_bounds__(RB) void reduce_partials(const double *__restrict__
         double s = 0.0;
         for (int g = 0; g < G; ++g)
             s += red[g][t];
-        rep_sums[(uint64_t)blockIdx.x * W + t] = s;
+        out[((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * W + t] = s;
     }
+}
+
+template <int W>
+hipError_t launch_reduce_w(const PriceLaunch &L, double *rep_sums, hipStream_t stream)
+{
+    const uint32_t chunks = (L.blocks_per_rep + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
+    if (chunks <= 1) {
+        hipLaunchKernelGGL(reduce_partials<W>, dim3(1, L.n_reps), dim3(RB), 0, stream, L.partials,
+                           L.blocks_per_rep, L.blocks_per_rep, rep_sums);
+        return hipGetLastError();
+    }
+    if (L.reduce_tmp == nullptr)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reduce_partials<W>, dim3(chunks, L.n_reps), dim3(RB), 0, stream,
+                       L.partials, L.blocks_per_rep, REDUCE_CHUNK, L.reduce_tmp);
+    hipLaunchKernelGGL(reduce_partials<W>, dim3(1, L.n_reps), dim3(RB), 0, stream,
+                       (const double *)L.reduce_tmp, chunks, chunks, rep_sums);
+    return hipGetLastError();
 }
 
 // Plain bump-and-revalue: per-path central differences of stored payoff rows.
@@ -874,13 +897,8 @@ hipError_t launch_reduce_rows(const double *partials, uint32_t rows, uint32_t w,
 
 hipError_t launch_reduce(const PriceLaunch &L, double *rep_sums, hipStream_t stream)
 {
-    if (L.cv)
-        hipLaunchKernelGGL(reduce_partials<N_ACC_CV>, dim3(L.n_reps), dim3(RB), 0, stream,
-                           L.partials, L.blocks_per_rep, rep_sums);
-    else
-        hipLaunchKernelGGL(reduce_partials<N_ACC>, dim3(L.n_reps), dim3(RB), 0, stream,
-                           L.partials, L.blocks_per_rep, rep_sums);
-    return hipGetLastError();
+    return L.cv ? launch_reduce_w<N_ACC_CV>(L, rep_sums, stream)
+                : launch_reduce_w<N_ACC>(L, rep_sums, stream);
 }
 
 } // namespace heston

@@ -25,6 +25,7 @@ struct heston_ctx {
     DevBuf pay, bump_partials, bump_sums, step_w;
     DevBuf geo_buf, geo_partials, geo_steps; // geometric-average control
     DevBuf exact_scratch;                    // exact sampler: Re Phi per lane
+    DevBuf reduce_tmp;                       // first-level sums of long reductions
     DevBuf batch_opts, batch_items, batch_partials, batch_sums, batch_counter, batch_scratch;
     double *host_sums = nullptr; // pinned
     size_t host_sums_bytes = 0;
