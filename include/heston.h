@@ -105,7 +105,9 @@ enum { HESTON_RNG_PHILOX = 0, HESTON_RNG_SOBOL_BRIDGE = 1 };
  * HESTON_EXACT_MAX_STEPS steps; its inputs are laid out per (step, path) as
  * Philox blocks with counter (step, lo32 path, hi32 path, 5 + 256 k).  Paths
  * whose draws leave the sampler's numerical range (see exact_kernel.hip) make
- * the call fail with HESTON_UNSUPPORTED.
+ * the call fail with HESTON_UNSUPPORTED.  The context keeps a scratch array of
+ * 128 KiB per resident lane (min(n_paths rounded up to 256, 65536) lanes: up
+ * to 8 GiB), counted against its HBM budget.
  * Adjoint calls, batches and the server use the Milstein schemes only. */
 enum {
     HESTON_FULL_TRUNCATION = 0,
