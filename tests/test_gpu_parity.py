@@ -365,3 +365,44 @@ def test_geometric_rejected_by_adjoint_and_batch(hm, ctx):
         ctx.price_batch([dict(params=PB.__dict__, type=hm.GEO_ASIAN_PUT, n_steps=4, n_paths=100,
                               seed=1, want=1)], hm.Options())
     assert e.value.status == -5
+
+
+# --- the paper's tables, reproduced on the GPU -------------------------------
+
+def _gold():
+    import json
+    here = os.path.dirname(os.path.abspath(__file__))
+    return json.load(open(os.path.join(here, "golden", "paper_values.json")))
+
+
+@pytest.mark.parametrize("asian", [False, True], ids=["european", "asian"])
+def test_paper_milstein_tables(hm, ctx, asian):
+    """The paper's Milstein tables (paper parameters, absorption, 32 000 paths,
+    32 to 256 steps; 30-run mean and std): one FP64 run per row within 4
+    combined errors, as the oracle's pin."""
+    tab = _gold()["milstein_asian_cpu_32000_paths" if asian else
+                  "milstein_european_cpu_32000_paths"]
+    for N, val, std in zip(tab["steps"], tab["value"], tab["std"]):
+        opts = hm.Options(scheme=hm.ABSORPTION, greeks=hm.GREEKS_PATHWISE,
+                          fixings=paper_fixing_steps(N) if asian else None)
+        r = ctx.price_greeks(PP.__dict__, hm.ASIAN_CALL if asian else hm.EURO_CALL, 32000, N,
+                             1000 + N, opts)
+        assert abs(r["price"][0] - val) < 4 * math.hypot(r["price"][1], std), (N, r["price"])
+
+
+def test_paper_greeks_table(hm, ctx):
+    """FP32, 2^22 paths, 128 steps, absorption: the European pathwise Delta and
+    Rho against the analytic values of the paper's Greeks table (4 SE plus 0.2%
+    for the discretisation), the quarterly Asian ones against its
+    exact-simulation values (4 SE plus 0.5%: their own error is not printed)."""
+    g = _gold()["greeks_table"]
+    N = 128
+    opts = hm.Options(precision=hm.FP32, scheme=hm.ABSORPTION, greeks=hm.GREEKS_PATHWISE)
+    r = ctx.price_greeks(PP.__dict__, hm.EURO_CALL, 1 << 22, N, 7, opts)
+    for k, ref in (("pw_delta", g["european"]["delta"]), ("pw_rho", g["european"]["rho"])):
+        assert abs(r[k][0] - ref) < 4 * r[k][1] + 0.002 * ref, (k, r[k], ref)
+    opts = hm.Options(precision=hm.FP32, scheme=hm.ABSORPTION, greeks=hm.GREEKS_PATHWISE,
+                      fixings=paper_fixing_steps(N))
+    r = ctx.price_greeks(PP.__dict__, hm.ASIAN_CALL, 1 << 22, N, 8, opts)
+    for k, ref in (("pw_delta", g["asian"]["ex_delta"]), ("pw_rho", g["asian"]["ex_rho"])):
+        assert abs(r[k][0] - ref) < 4 * r[k][1] + 0.005 * ref, (k, r[k], ref)
