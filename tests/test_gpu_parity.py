@@ -406,3 +406,19 @@ def test_paper_greeks_table(hm, ctx):
     r = ctx.price_greeks(PP.__dict__, hm.ASIAN_CALL, 1 << 22, N, 8, opts)
     for k, ref in (("pw_delta", g["asian"]["ex_delta"]), ("pw_rho", g["asian"]["ex_rho"])):
         assert abs(r[k][0] - ref) < 4 * r[k][1] + 0.005 * ref, (k, r[k], ref)
+
+
+@pytest.mark.parametrize("asian", [False, True], ids=["european", "asian"])
+def test_paper_path_count_tables(hm, ctx, asian):
+    """The paper's path-count tables (paper parameters, absorption, 128 steps,
+    4000 to 32 000 paths; 30-run mean and std): one FP64 run per row within 4
+    combined errors."""
+    tab = _gold()["milstein_asian_paths_128_steps" if asian else
+                  "milstein_european_paths_128_steps"]
+    N = 128
+    opts = hm.Options(scheme=hm.ABSORPTION, greeks=hm.GREEKS_PATHWISE,
+                      fixings=paper_fixing_steps(N) if asian else None)
+    for n, val, std in zip(tab["paths"], tab["value"], tab["std"]):
+        r = ctx.price_greeks(PP.__dict__, hm.ASIAN_CALL if asian else hm.EURO_CALL, n, N,
+                             2000 + n, opts)
+        assert abs(r["price"][0] - val) < 4 * math.hypot(r["price"][1], std), (n, r["price"])

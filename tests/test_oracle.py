@@ -314,6 +314,20 @@ def test_milstein_reproduces_paper_tables(asian):
         assert abs(m - val) < 4 * math.hypot(se, std), (N, m, se, val, std)
 
 
+@pytest.mark.parametrize("asian", [False, True])
+def test_milstein_reproduces_paper_path_count_tables(asian):
+    """Paper parameters, 128 steps, 4000 to 32 000 paths: the CPU Milstein
+    prices of the paper's path-count tables (30-run mean and std)."""
+    key = "milstein_asian_paths_128_steps" if asian else "milstein_european_paths_128_steps"
+    tab = GOLD[key]
+    for n, val, std in zip(tab["paths"], tab["value"], tab["std"]):
+        rec = oracle.simulate(PP, AC if asian else EC, 128, seed=2000 + n, n_paths=n,
+                              fixings=paper_fixing_steps(128) if asian else None,
+                              mode=oracle.ABSORB, threads=8)
+        m, se = oracle.mean_se(rec[:, 3])
+        assert abs(m - val) < 4 * math.hypot(se, std), (n, m, se, val, std)
+
+
 @pytest.mark.slow
 def test_milstein_asian_matches_paper_exact_simulation():
     g = GOLD["asian_bk_qmc_512"]
