@@ -160,3 +160,23 @@ def test_full_size_sampled_paths(hm, ctx):
         m, se = oracle.mean_se(full[:, k])
         assert r[name][0] == pytest.approx(m, rel=1e-9), name
         assert r[name][1] == pytest.approx(se, rel=1e-6), name
+
+
+@pytest.mark.parametrize("asian", [False, True], ids=["european", "asian"])
+def test_paper_exact_simulation_tables(hm, ctx, asian):
+    """The Monte-Carlo column of the paper's exact-simulation tables (paper
+    parameters; European in one step, the quarterly Asian in four; 64 to 2048
+    paths, 30-run mean and std): one run per row within 4 combined errors.
+    The printed stds are about a fifth of a plain estimator's error at these
+    path counts (they imply a control variate in the paper's implementation),
+    so this run's own standard error dominates the bar."""
+    import json
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    tab = json.load(open(os.path.join(here, "golden", "paper_values.json")))[
+        "exact_asian_mc" if asian else "exact_european_mc"]
+    opts = hm.Options(scheme=hm.EXACT, greeks=hm.GREEKS_PATHWISE)
+    for n, val, std in zip(tab["paths"], tab["value"], tab["std"]):
+        r = ctx.price_greeks(PP.__dict__, oracle.ASIAN_CALL if asian else oracle.EURO_CALL, n,
+                             4 if asian else 1, 3000 + n, opts)
+        assert abs(r["price"][0] - val) < 4 * math.hypot(r["price"][1], std), (n, r["price"])

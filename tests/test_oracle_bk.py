@@ -77,3 +77,15 @@ def test_bk_asian_matches_paper_exact_simulation():
     g = GOLD["asian_bk_qmc_512"]
     v, se = bk.price(PP, True, 3000, seed=12, times=g["fixing_times"])
     assert abs(v - g["value"]) < 3.5 * math.hypot(se, g["std"])
+
+
+@pytest.mark.parametrize("asian", [False, True], ids=["european", "asian"])
+def test_bk_reproduces_paper_mc_columns(asian):
+    """The Monte-Carlo column of the paper's exact-simulation tables (64 to 2048
+    paths; 30-run mean and std), one control-variate run per row within 4
+    combined errors."""
+    tab = GOLD["exact_asian_mc" if asian else "exact_european_mc"]
+    times = GOLD["asian_bk_qmc_512"]["fixing_times"] if asian else None
+    for n, val, std in zip(tab["paths"], tab["value"], tab["std"]):
+        v, se = bk.price(PP, asian, n, seed=4000 + n, times=times)
+        assert abs(v - val) < 4 * math.hypot(se, std), (n, v, se, val, std)
