@@ -40,12 +40,17 @@ __device__ __forceinline__ bool is_fixing(const uint32_t *fix_bits, uint32_t jf)
 }
 
 // Normals of steps (j, j+1) from one Philox block: counter (j >> 1, lo32 p, hi32 p, 0).
-template <class R>
+// LOG2_SCALED (single precision only): the normals come divided by
+// sqrt(2 ln 2) (box_muller_log2).
+template <class R, bool LOG2_SCALED = false>
 __device__ __forceinline__ void philox_normals(uint32_t j, uint32_t plo, uint32_t phi, uint32_t k0,
                                                uint32_t k1, R &za0, R &zb0, R &za1, R &zb1)
 {
     const U4 w = philox4x32_10(U4{j >> 1, plo, phi, 0u}, k0, k1);
-    if constexpr (sizeof(R) == 4) {
+    if constexpr (sizeof(R) == 4 && LOG2_SCALED) {
+        box_muller_log2(uniform_f32(w.x), uniform_f32(w.y), za0, zb0);
+        box_muller_log2(uniform_f32(w.z), uniform_f32(w.w), za1, zb1);
+    } else if constexpr (sizeof(R) == 4) {
         box_muller(uniform_f32(w.x), uniform_f32(w.y), za0, zb0);
         box_muller(uniform_f32(w.z), uniform_f32(w.w), za1, zb1);
     } else {

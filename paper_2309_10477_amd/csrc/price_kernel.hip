@@ -301,11 +301,16 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         }
     };
 
+    // Multipliers of the normals: Z1 / ln 2 (times FT_SCALE) and the
+    // correlation; the single-precision Philox walk folds the factor
+    // sqrt(2 ln 2) of its Box-Muller radius into them.
+    R z1c = log2e * FT_SCALE<R, FT>, rhoc = rho, rhobc = rho_bar;
+
     // One Milstein step given the independent normals (za, zb) of step j.
     auto step = [&](uint32_t j, R za, R zb) {
         constexpr R FS = FT_SCALE<R, FT>;
-        const R z1l = za * (log2e * FS);
-        const R z2 = rho * za + rho_bar * zb;
+        const R z1l = za * z1c;
+        const R z2 = rhoc * za + rhobc * zb;
         const R z2m1 = z2 * z2 - R(1);
         const R ab = gb.ktdt2 + gb.qdt2 * z2m1, sb = (gb.sdt * FS) * z2;
         if constexpr (SCH == 3) {
@@ -361,16 +366,23 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         // Paths below 2^32 have a zero high counter word: the first round's
         // second product is then zero and the compiler keeps it scalar.
         const uint32_t plo = (uint32_t)p, phi = L.wide_paths ? (uint32_t)(p >> 32) : 0u;
+        constexpr bool SCALED = sizeof(R) == 4;
+        if constexpr (SCALED) {
+            constexpr double NS = 1.17741002251547469101; // sqrt(2 ln 2)
+            z1c = (R)(LOG2E * (double)FT_SCALE<R, FT> * NS);
+            rhoc = (R)(L.rho * NS);
+            rhobc = (R)(L.rho_bar * NS);
+        }
         uint32_t j = 0;
         for (; j + 1 < N; j += 2) {
             R za0, zb0, za1, zb1;
-            philox_normals<R>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
+            philox_normals<R, SCALED>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
             step(j, za0, zb0);
             step(j + 1, za1, zb1);
         }
         if (j < N) {
             R za0, zb0, za1, zb1;
-            philox_normals<R>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
+            philox_normals<R, SCALED>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
             step(j, za0, zb0);
         }
     } else {
