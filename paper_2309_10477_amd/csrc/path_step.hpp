@@ -20,12 +20,13 @@ template <class R> __device__ __forceinline__ Coef<R> coef(const StepCoef &s)
 // One step of (x = ln S/S0, V) on grid c: the log-price step carries no
 // Milstein term; the variance step carries mil = sigma^2 dt (Z2^2 - 1) / 4.
 // sz2 = sigma Z2.  FT: full truncation (V+ in drift and diffusion, V carried);
-// otherwise absorption (V clamped at 0 after the step).
+// otherwise absorption (V clamped at 0 after the step).  sdt is the time step
+// under the square root: dt, or dt NS^2 with scaled normals (NormalScale).
 template <class R, bool FT>
-__device__ __forceinline__ void mil_step(R &x, R &v, const Coef<R> &c, R z1, R sz2, R mil)
+__device__ __forceinline__ void mil_step(R &x, R &v, const Coef<R> &c, R z1, R sz2, R mil, R sdt)
 {
     const R vp = v > R(0) ? v : R(0);
-    const R s = fast_sqrt(vp * c.dt);
+    const R s = fast_sqrt(vp * sdt);
     x += (c.r_dt - c.half_dt * vp) + s * z1;
     const R vb = FT ? v : vp;
     v = vb + (c.ktdt - c.kdt * vp) + sz2 * s + mil;
@@ -57,6 +58,22 @@ __device__ __forceinline__ void philox_normals(uint32_t j, uint32_t plo, uint32_
         box_muller(uniform_f64(w.x), uniform_f64(w.y), za0, zb0);
         box_muller(uniform_f64(w.z), uniform_f64(w.w), za1, zb1);
     }
+}
+
+// Constants that multiply the normals.  Single precision takes its Philox
+// normals divided by NS = sqrt(2 ln 2) (box_muller_log2) and folds NS into
+// them: rho and rho_bar turn the scaled pair into Z2; the square root is taken
+// of V+ dt NS^2, which puts NS onto the log-price's Z1; sigma / NS then leaves
+// the variance diffusion sigma Z2 sqrt(V+ dt) unchanged.  Double precision
+// keeps the plain normals (NS = 1).
+template <class R> struct NormalScale {
+    R rho, rho_bar, sigma, sdt, ns;
+};
+template <class R> __device__ __forceinline__ NormalScale<R> normal_scale(const PathConsts &k)
+{
+    const double ns = sizeof(R) == 4 ? 1.17741002251547469101 : 1.0; // sqrt(2 ln 2)
+    return NormalScale<R>{(R)(k.rho * ns), (R)(k.rho_bar * ns), (R)(k.sigma / ns),
+                          (R)(k.c.dt * ns * ns), (R)ns};
 }
 
 __host__ __device__ inline PathConsts path_consts(const PriceLaunch &L)
@@ -91,7 +108,7 @@ __device__ __forceinline__ void forward_path(const PathConsts &k, uint64_t p, R 
                                              uint32_t every)
 {
     const Coef<R> c = coef<R>(k.c);
-    const R rho = (R)k.rho, rho_bar = (R)k.rho_bar, sigma = (R)k.sigma;
+    const NormalScale<R> ns = normal_scale<R>(k);
     const uint32_t k0 = (uint32_t)k.seed, k1 = (uint32_t)(k.seed >> 32);
     const uint32_t plo = (uint32_t)p, phi = k.wide ? (uint32_t)(p >> 32) : 0u;
     const uint32_t N = k.n_steps;
@@ -100,8 +117,8 @@ __device__ __forceinline__ void forward_path(const PathConsts &k, uint64_t p, R 
     A = R(0);
     B = R(0);
     auto step = [&](uint32_t j, R za, R zb) {
-        const R z2 = rho * za + rho_bar * zb;
-        mil_step<R, FT>(x, v, c, za, sigma * z2, c.qdt * (z2 * z2 - R(1)));
+        const R z2 = ns.rho * za + ns.rho_bar * zb;
+        mil_step<R, FT>(x, v, c, za, ns.sigma * z2, c.qdt * (z2 * z2 - R(1)), ns.sdt);
         if constexpr (ASIAN) {
             if (is_fixing(k.fix_bits, j + 1)) {
                 const R e = fast_exp(x);
@@ -117,7 +134,7 @@ __device__ __forceinline__ void forward_path(const PathConsts &k, uint64_t p, R 
             ck[(2 * cc + 1) * stride + row] = v;
         }
         R za0, zb0, za1, zb1;
-        philox_normals<R>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
+        philox_normals<R, sizeof(R) == 4>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
         step(j, za0, zb0);
         if (j + 1 < N)
             step(j + 1, za1, zb1);
@@ -159,7 +176,9 @@ __device__ __forceinline__ void adjoint_path(const PathConsts &k, uint64_t p, co
     const uint32_t N = k.n_steps;
     const uint64_t nck = ckpt_count(N, SEG);
     const Coef<R> c = coef<R>(k.c);
-    const R rho = (R)k.rho, rho_bar = (R)k.rho_bar, sigma = (R)k.sigma, theta = (R)k.theta;
+    const NormalScale<R> ns = normal_scale<R>(k);
+    const R sigma = (R)k.sigma, theta = (R)k.theta;
+    const R half_dt_ns = (R)(0.5 * k.c.dt * (double)ns.ns); // ds/dV+ = half_dt_ns rs / NS
     const R rho_ratio = (R)(k.rho_bar > 0 ? k.rho / k.rho_bar : 0.0); // -d rho_bar / d rho
     const R half_sigma_dt = (R)(0.5 * k.sigma * k.c.dt);              // d(qdt)/d sigma
     const R two_qdt = (R)(2.0 * k.c.quarter_sigma2_dt);
@@ -195,20 +214,23 @@ __device__ __forceinline__ void adjoint_path(const PathConsts &k, uint64_t p, co
         for (int q = 0; q < SEG; q += 2) {
             if ((uint32_t)q < len) {
                 R za[2], zb[2];
-                philox_normals<R>(s0 + q, plo, phi, k0, k1, za[0], zb[0], za[1], zb[1]);
+                philox_normals<R, sizeof(R) == 4>(s0 + q, plo, phi, k0, k1, za[0], zb[0], za[1],
+                                                  zb[1]);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int qq = q + h;
                     if ((uint32_t)qq < len) {
-                        const R z2 = rho * za[h] + rho_bar * zb[h];
+                        const R z2 = ns.rho * za[h] + ns.rho_bar * zb[h];
                         const R vp = v > R(0) ? v : R(0);
                         a_vp[qq] = vp;
                         a_za[qq] = za[h];
                         a_zb[qq] = zb[h];
                         const R vb = FT ? v : vp;
-                        const R vpre = vb + (c.ktdt - c.kdt * vp) + (sigma * z2) * fast_sqrt(vp * c.dt) +
+                        const R vpre = vb + (c.ktdt - c.kdt * vp) +
+                                       (ns.sigma * z2) * fast_sqrt(vp * ns.sdt) +
                                        c.qdt * (z2 * z2 - R(1));
-                        mil_step<R, FT>(x, v, c, za[h], sigma * z2, c.qdt * (z2 * z2 - R(1)));
+                        mil_step<R, FT>(x, v, c, za[h], ns.sigma * z2, c.qdt * (z2 * z2 - R(1)),
+                                        ns.sdt);
                         a_clip[qq] = !FT && !(vpre > R(0));
                         a_f[qq] = (ASIAN && is_fixing(k.fix_bits, s0 + qq + 1)) ? c_fix * fast_exp(x)
                                                                                : R(0);
@@ -224,16 +246,18 @@ __device__ __forceinline__ void adjoint_path(const PathConsts &k, uint64_t p, co
                 if (!FT && a_clip[q])
                     vbar = R(0); // V_{j+1} = max(pre, 0) with pre <= 0
                 sum_xbar += xbar;
+                // za, zb are the scaled normals (true ones times 1 / NS)
                 const R vp = a_vp[q], za = a_za[q], zb = a_zb[q];
-                const R z2 = rho * za + rho_bar * zb;
-                const R dz2 = za - rho_ratio * zb;
+                const R z2 = ns.rho * za + ns.rho_bar * zb;
+                const R dz2 = za - rho_ratio * zb; // dZ2/drho / NS
                 const bool pos = vp > R(0);
-                // s = sqrt(V+ dt) and ds/dV+ = dt / (2 s) from one reciprocal square root
+                // s = sqrt(V+ dt) and NS ds/dV+ = NS dt / (2 s) from one reciprocal
+                // square root
                 const R s2 = vp * c.dt;
                 const R rs = pos ? fast_rsqrt(s2) : R(0);
                 const R s = s2 * rs;
-                const R dsdv = c.half_dt * rs;
-                const R g = xbar * (za * dsdv - c.half_dt) + vbar * (sigma * z2 * dsdv - c.kdt);
+                const R dsdv = half_dt_ns * rs;
+                const R g = xbar * (za * dsdv - c.half_dt) + vbar * (ns.sigma * z2 * dsdv - c.kdt);
                 kbar += vbar * (theta - vp);
                 thbar += vbar;
                 sbar += vbar * (s * z2 + half_sigma_dt * (z2 * z2 - R(1)));
@@ -249,7 +273,7 @@ __device__ __forceinline__ void adjoint_path(const PathConsts &k, uint64_t p, co
     out[4] = (double)kbar * k.c.dt;
     out[5] = (double)thbar * k.c.kappa_dt;
     out[6] = (double)sbar;
-    out[7] = (double)rhobar;
+    out[7] = (double)rhobar * (double)ns.ns;
 }
 
 } // namespace heston
