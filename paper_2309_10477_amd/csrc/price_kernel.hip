@@ -189,35 +189,58 @@ __device__ __forceinline__ double fast_log(double x) { return log(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
-// One QE step of one scenario; z1l = Zs / ln 2, zv the normal of the
-// quadratic branch, uv the uniform of the exponential branch.  Both branches
-// are evaluated and one selected: psi = s2 / m^2 <= 3/2 takes the scaled
-// squared normal a (b + zv)^2, else V' is 0 with probability
-// p = (psi-1)/(psi+1) and exponential above it.
-template <class R>
-__device__ __forceinline__ void qe_step(R &y, R &w, const QEGrid<R> &g, R z1l, R zv, R uv)
+// One QE step of one scenario, in two parts; z1l = Zs / ln 2, zv the normal
+// of the quadratic branch, uv the uniform of the exponential branch.
+// psi = s2 / m^2 <= 3/2 takes the scaled squared normal a (b + zv)^2, else V'
+// is 0 with probability p = (psi-1)/(psi+1) and exponential above it.
+// qe_pre gives m, s2 and psi; qe_post evaluates a branch only when some lane
+// of the wave takes it (quad, expo: wave-uniform votes over all scenarios).
+// Away from zero variance every lane takes the quadratic branch, so whole
+// waves skip the exponential one and its logarithm; each lane still selects
+// by its own psi, so the result is that of evaluating both.
+template <class R> struct QEPre {
+    R m, s2, psi;
+};
+
+template <class R> __device__ __forceinline__ QEPre<R> qe_pre(R w, const QEGrid<R> &g)
 {
     const R m = w * g.E + g.mth;
     const R s2 = w * g.cs1 + g.cs0;
     const R rm = fast_rcp(m);
-    const R psi = s2 * rm * rm;
-    // quadratic branch
-    const R inv = R(2) * m * m * fast_rcp(s2);
-    const R b2 = inv - R(1) + fast_sqrt(inv * (inv - R(1)));
-    const R b = fast_sqrt(b2);
-    const R a = m * fast_rcp(R(1) + b2);
-    const R bz = b + zv;
-    const R wq = a * bz * bz;
-    // exponential branch: p = (psi - 1) / (psi + 1), 1 - p = 2 / (psi + 1),
-    // 1 / beta = m (psi + 1) / 2; uv <= p is tested as uv (psi + 1) <= psi - 1
-    // and ln((1 - p) / (1 - uv)) as -ln((psi + 1)(1 - uv) / 2)
-    const R pp1 = psi + R(1);
-    const R we = uv * pp1 <= psi - R(1)
-                     ? R(0)
-                     : -(R(0.5) * m * pp1) * fast_log(R(0.5) * pp1 * (R(1) - uv));
+    return QEPre<R>{m, s2, s2 * rm * rm};
+}
+
+template <class R>
+__device__ __forceinline__ void qe_post(R &y, R &w, const QEGrid<R> &g, const QEPre<R> &q, R z1l,
+                                        R zv, R uv, bool quad, bool expo)
+{
+    const R m = q.m, s2 = q.s2, psi = q.psi;
+    R wq = R(0), we = R(0);
+    if (quad) {
+        const R inv = R(2) * m * m * fast_rcp(s2);
+        const R b2 = inv - R(1) + fast_sqrt(inv * (inv - R(1)));
+        const R b = fast_sqrt(b2);
+        const R a = m * fast_rcp(R(1) + b2);
+        const R bz = b + zv;
+        wq = a * bz * bz;
+    }
+    if (expo) {
+        // p = (psi - 1) / (psi + 1), 1 - p = 2 / (psi + 1), 1 / beta = m (psi + 1) / 2;
+        // uv <= p is tested as uv (psi + 1) <= psi - 1 and ln((1 - p) / (1 - uv))
+        // as -ln((psi + 1)(1 - uv) / 2)
+        const R pp1 = psi + R(1);
+        we = uv * pp1 <= psi - R(1) ? R(0)
+                                    : -(R(0.5) * m * pp1) * fast_log(R(0.5) * pp1 * (R(1) - uv));
+    }
     const R wn = psi <= R(1.5) ? wq : we;
     y = y + g.k0 + g.k1 * w + g.k2 * wn + fast_sqrt(g.k3 * w + g.k4 * wn) * z1l;
     w = wn;
+}
+
+// Wave-uniform: does some lane take the quadratic (resp. exponential) branch?
+template <class R> __device__ __forceinline__ bool any_lane(bool c)
+{
+    return __builtin_amdgcn_ballot_w64(c) != 0u;
 }
 
 template <class R, int RNG, int AV, bool BUMPS, int SCH>
@@ -351,12 +374,26 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
                 uv = uniform_f64(q.z);
             }
             const R z1l = zs * log2e;
-            qe_step<R>(y, w, qb, z1l, zv, uv);
+            const QEPre<R> q0 = qe_pre<R>(w, qb);
+            QEPre<R> q1{}, q2{}, q3{}, q4{};
+            bool lo = q0.psi <= R(1.5), hi = !lo;
             if constexpr (BUMPS) {
-                qe_step<R>(yv0, wv0, qb, z1l, zv, uv);
-                qe_step<R>(yv1, wv1, qb, z1l, zv, uv);
-                qe_step<R>(yt0, wt0, qu, z1l, zv, uv);
-                qe_step<R>(yt1, wt1, qd, z1l, zv, uv);
+                q1 = qe_pre<R>(wv0, qb);
+                q2 = qe_pre<R>(wv1, qb);
+                q3 = qe_pre<R>(wt0, qu);
+                q4 = qe_pre<R>(wt1, qd);
+                for (const R ps : {q1.psi, q2.psi, q3.psi, q4.psi}) {
+                    lo = lo || ps <= R(1.5);
+                    hi = hi || !(ps <= R(1.5));
+                }
+            }
+            const bool quad = any_lane<R>(lo), expo = any_lane<R>(hi);
+            qe_post<R>(y, w, qb, q0, z1l, zv, uv, quad, expo);
+            if constexpr (BUMPS) {
+                qe_post<R>(yv0, wv0, qb, q1, z1l, zv, uv, quad, expo);
+                qe_post<R>(yv1, wv1, qb, q2, z1l, zv, uv, quad, expo);
+                qe_post<R>(yt0, wt0, qu, q3, z1l, zv, uv, quad, expo);
+                qe_post<R>(yt1, wt1, qd, q4, z1l, zv, uv, quad, expo);
             }
             fixing(j);
         }
