@@ -64,8 +64,10 @@ __device__ __forceinline__ void box_muller(float ua, float ub, float &za, float 
     za = rad * __builtin_amdgcn_cosf(ub);
     zb = rad * __builtin_amdgcn_sinf(ub);
 }
-// The same pair divided by sqrt(2 ln 2): sqrt(-log2 ua) (cos 2 pi ub, sin 2 pi ub),
-// for callers that fold the factor into the constants the normals multiply.
+// The same pair divided by SQRT_2LN2 = sqrt(2 ln 2): sqrt(-log2 ua) (cos 2 pi ub,
+// sin 2 pi ub), for callers that fold the factor into the constants the
+// normals multiply.
+constexpr double SQRT_2LN2 = 1.17741002251547469101;
 __device__ __forceinline__ void box_muller_log2(float ua, float ub, float &za, float &zb)
 {
     const float rad = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(ua));

@@ -71,7 +71,7 @@ template <class R> struct NormalScale {
 };
 template <class R> __device__ __forceinline__ NormalScale<R> normal_scale(const PathConsts &k)
 {
-    const double ns = sizeof(R) == 4 ? 1.17741002251547469101 : 1.0; // sqrt(2 ln 2)
+    const double ns = sizeof(R) == 4 ? SQRT_2LN2 : 1.0;
     return NormalScale<R>{(R)(k.rho * ns), (R)(k.rho_bar * ns), (R)(k.sigma / ns),
                           (R)(k.c.dt * ns * ns), (R)ns};
 }

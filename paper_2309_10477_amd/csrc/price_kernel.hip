@@ -405,7 +405,7 @@ __global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
         const uint32_t plo = (uint32_t)p, phi = L.wide_paths ? (uint32_t)(p >> 32) : 0u;
         constexpr bool SCALED = sizeof(R) == 4;
         if constexpr (SCALED) {
-            constexpr double NS = 1.17741002251547469101; // sqrt(2 ln 2)
+            constexpr double NS = SQRT_2LN2;
             z1c = (R)(LOG2E * (double)FT_SCALE<R, FT> * NS);
             rhoc = (R)(L.rho * NS);
             rhobc = (R)(L.rho_bar * NS);
