@@ -243,8 +243,13 @@ template <class R> __device__ __forceinline__ bool any_lane(bool c)
     return __builtin_amdgcn_ballot_w64(c) != 0u;
 }
 
+// Single-precision QE asks for six waves per SIMD: left to itself the compiler
+// spends 140-147 VGPRs on it (three waves); bounded, it fits in 76 without
+// spilling and runs 4% faster.  The other variants keep the default.
 template <class R, int RNG, int AV, bool BUMPS, int SCH>
-__global__ __launch_bounds__(BLOCK) void price_kernel(const PriceLaunch L)
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void price_kernel(
+    const PriceLaunch L)
 {
     // AV: 0 European, 1 arithmetic average, 2 geometric average over the
     // fixings, 3 arithmetic average with the geometric one as its control.
