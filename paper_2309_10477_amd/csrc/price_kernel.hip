@@ -237,8 +237,9 @@ __device__ __forceinline__ void qe_post(R &y, R &w, const QEGrid<R> &g, const QE
     w = wn;
 }
 
-// Wave-uniform: does some lane take the quadratic (resp. exponential) branch?
-template <class R> __device__ __forceinline__ bool any_lane(bool c)
+// Wave-uniform: does some lane of the wave have c set?  (Every lane of the
+// wave runs the step loop, so the vote covers all 64.)
+__device__ __forceinline__ bool any_lane(bool c)
 {
     return __builtin_amdgcn_ballot_w64(c) != 0u;
 }
@@ -392,7 +393,7 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
                     hi = hi || !(ps <= R(1.5));
                 }
             }
-            const bool quad = any_lane<R>(lo), expo = any_lane<R>(hi);
+            const bool quad = any_lane(lo), expo = any_lane(hi);
             qe_post<R>(y, w, qb, q0, z1l, zv, uv, quad, expo);
             if constexpr (BUMPS) {
                 qe_post<R>(yv0, wv0, qb, q1, z1l, zv, uv, quad, expo);
