@@ -50,7 +50,7 @@ ALU_PEAK_OPS = 256 * 128 * 2.4e9
 # a 256 MiB device copy reads under the same counters); see
 # profiles/price_kernel_asian_2p20x252_fp32_bumps_hbm_counters.md.  Set to None
 # whenever the kernel changes until the counters are taken again.
-TRAFFIC_BYTES_PER_LAUNCH = 838_564
+TRAFFIC_BYTES_PER_LAUNCH = 838_265
 
 
 def parse():

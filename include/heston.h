@@ -184,7 +184,9 @@ typedef struct heston_opts {
     uint32_t qmc_replicates; /* Sobol: R digitally shifted replicates; n_paths must
                                 be a multiple of R (points per replicate = n_paths/R) */
     const uint32_t *sobol_directions; /* Sobol: host array [sobol_dims][32] of 30-bit
-                                direction numbers v[d][b] (only b < 30 read), the
+                                direction numbers v[d][b] (only b < 30 read; one
+                                wider than 30 bits in the first 2 n_steps rows is
+                                HESTON_INVALID_ARGUMENT), the
                                 Joe-Kuo table in the layout of torch's SobolEngine
                                 state; dimension 2k feeds bridge node k of the price
                                 motion and 2k+1 that of the variance motion */

@@ -264,6 +264,11 @@ heston_status check_request(const Request &q)
             return fail(HESTON_UNSUPPORTED, "more than 2^30 points per replicate");
         if (!o.sobol_directions || o.sobol_dims < 2 * q.n_steps)
             return fail(HESTON_INVALID_ARGUMENT, "need sobol_directions for 2*n_steps dimensions");
+        // the kernels map 30-bit coordinates to normals (the upper half by
+        // complementing the 30 bits): wider direction numbers are rejected
+        for (size_t k = 0; k < (size_t)2 * q.n_steps * 32; ++k)
+            if (k % 32 < 30 && (o.sobol_directions[k] >> 30) != 0u)
+                return fail(HESTON_INVALID_ARGUMENT, "sobol_directions must be 30-bit numbers");
         if (q.n_paths / o.qmc_replicates < 2)
             return fail(HESTON_INVALID_ARGUMENT, "need >= 2 points per replicate");
     }

@@ -54,18 +54,31 @@ __device__ __forceinline__ uint32_t sobol_coord(const uint32_t *__restrict__ dir
 // single precision keeps full relative precision in both tails.
 template <class R> __device__ __forceinline__ R sobol_normal(uint32_t x)
 {
-    const bool upper = x >= (1u << 29);
-    const uint32_t xs = upper ? 0x3FFFFFFFu - x : x;
-    const R z = inv_normal_lower(((R)xs + R(0.5)) * R(0x1p-30));
-    return upper ? -z : z;
+    if constexpr (sizeof(R) == 4) {
+        // bit 29 marks the upper half: m is all ones there, and the mirror
+        // 0x3FFFFFFF - x of a 30-bit x is x with its 30 bits complemented;
+        // the sign is restored by flipping the float's sign bit (no selects)
+        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)x, 29, 1);
+        const uint32_t xs = x ^ (m & 0x3FFFFFFFu);
+        const float z = inv_normal_lower(((float)xs + 0.5f) * 0x1p-30f);
+        return __uint_as_float(__float_as_uint(z) ^ (m & 0x80000000u));
+    } else {
+        const bool upper = x >= (1u << 29);
+        const uint32_t xs = upper ? 0x3FFFFFFFu - x : x;
+        const R z = inv_normal_lower(((R)xs + R(0.5)) * R(0x1p-30));
+        return upper ? -z : z;
+    }
 }
 
 // The low six Gray-code bits of a lane's point select direction numbers
 // v[0..5]; `m` holds all-ones or zero masks for them.
 __device__ __forceinline__ uint32_t sobol_low(const uint32_t *__restrict__ v, const uint32_t m[6])
 {
-    return (m[0] & v[0]) ^ (m[1] & v[1]) ^ (m[2] & v[2]) ^ (m[3] & v[3]) ^ (m[4] & v[4]) ^
-           (m[5] & v[5]);
+    uint32_t x = m[0] & v[0];
+#pragma unroll
+    for (int b = 1; b < 6; ++b)
+        x = __builtin_amdgcn_bitop3_b32(m[b], v[b], x, 0x6A); // (m & v) ^ x
+    return x;
 }
 
 // The fused kernel carries each scenario's state scaled: y = ln(S/S0) / ln 2,

@@ -422,3 +422,25 @@ def test_paper_path_count_tables(hm, ctx, asian):
         r = ctx.price_greeks(PP.__dict__, hm.ASIAN_CALL if asian else hm.EURO_CALL, n, N,
                              2000 + n, opts)
         assert abs(r["price"][0] - val) < 4 * math.hypot(r["price"][1], std), (n, r["price"])
+
+
+def test_sobol_directions_wider_than_30_bits_rejected(hm, ctx):
+    """The kernels read 30-bit coordinates (the upper half of the unit interval is
+    mapped by complementing those 30 bits), so a direction number with bit 30 or
+    31 set is an invalid argument; the same table with it cleared is accepted."""
+    import ctypes
+    N = 8
+    o = hm._OptsHolder(hm.Options(rng=hm.SOBOL_BRIDGE, qmc_replicates=2), N)
+    dirs = o.dirs.copy()
+    dirs[2 * N - 1, 3] |= np.uint32(1 << 30)
+    o.dirs = dirs
+    o.c.sobol_directions = dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    res = hm.CResult()
+    cp = hm._cparams(PB.__dict__)
+    st = hm.lib().heston_price_greeks_ex(ctx.handle, ctypes.byref(cp), 0, 512, N, 1,
+                                         ctypes.byref(o.c), ctypes.byref(res))
+    assert st == -1
+    dirs[2 * N - 1, 3] &= np.uint32((1 << 30) - 1)
+    st = hm.lib().heston_price_greeks_ex(ctx.handle, ctypes.byref(cp), 0, 512, N, 1,
+                                         ctypes.byref(o.c), ctypes.byref(res))
+    assert st == 0
