@@ -9,18 +9,19 @@ side takes those decisions in its own precision, so a path may only differ
 where the oracle's decision margin (the smallest such distance along the
 path) is below 1e-9 (FP64) or 1e-4 (FP32); such paths must stay rare.
 
-A QE variance step can amplify an earlier relative error of the variance (a
-step from a small variance into a large one: |dV'/dV| above 10 happens where
-vol of vol is high), and every later log-price increment uses those
-variances, so the rounding of a lower-precision evaluation grows along such
-paths.  The oracle reports each path's amplification a_p >= 1 (the largest
-growth of a relative variance perturbation into any later variance, in units
-of max(V, v0, theta)); the per-path bar is multiplied by a_p.  (Observed in
-FP32: a path with a_p = 52 differs by 2.5e-5 relative in V_T, and a correctly
-rounded binary32 CPU evaluation of the same formulas by 1.6e-5; a path with
-a_p = 418 differs by 1.1e-5 of S0 in a payoff: the size comes from the
-scheme's conditioning, not from the kernel.  At the Feller-satisfying
-parameters a_p stays near 1.)
+The FP64 bar is the plain 1e-12.  In binary32 a QE path can sit further
+than 1e-5 from the FP64 oracle for reasons of arithmetic alone: a QE variance
+step from a small variance into a large one amplifies earlier relative errors
+of the variance (|dV'/dV| above 10 where vol of vol is high), and every later
+log-price increment uses those variances.  tests/qe_binary32.py evaluates the
+kernel's formulas in binary32 on the CPU, and tests/test_qe_binary32.py shows
+there that such evaluations miss 1e-5 on amplified paths, by amounts that grow
+with the oracle's amplification a_p, and that three times the spread of a
+16-member Monte-Carlo-arithmetic ensemble bounds other binary32 evaluations.
+The FP32 bar per path and column is therefore
+max(1e-5 max(|oracle|, floor), 3 x that spread): where binary32 itself is
+exact to 1e-5 it is the plain bar, and nowhere is it wider than what a
+binary32 evaluation on the CPU shows for the same path.
 """
 import math
 
@@ -28,6 +29,7 @@ import numpy as np
 import pytest
 
 import oracle
+import qe_binary32
 from oracle import analytic
 from workloads import BASE
 
@@ -57,36 +59,48 @@ def ctx(hm):
     c.close()
 
 
-def compare(name, g, o, tol, floor, skip, amp=1.0):
-    err = np.abs(g - o) / (np.maximum(np.abs(o), floor) * amp)
-    bad = (err > tol) & ~skip
+def compare(name, g, o, bar, skip):
+    err = np.abs(g - o)
+    bad = (err > bar) & ~skip
     if bad.any():
-        i = int(np.argmax(np.where(bad, err, 0)))
+        i = int(np.argmax(np.where(bad, err / bar, 0)))
         raise AssertionError(f"{name}: {int(bad.sum())} paths off, worst path {i}: "
-                             f"gpu {g[i]!r} oracle {o[i]!r} rel {err[i]:.3e} > {tol}")
+                             f"gpu {g[i]!r} oracle {o[i]!r} |d| {err[i]:.3e} > bar {bar[i]:.3e}")
 
 
-def check(hm, ctx, p, opt_type, n, N, seed, prec, first=0, bumps=True):
+def check(hm, ctx, p, opt_type, n, N, seed, prec, first=0, bumps=True, n_total=None):
+    """Dumped records of paths first .. first+n-1 (of a launch over n_total
+    paths, default first + n) against the oracle's, every column (bump
+    scenarios re-simulated by the oracle)."""
     tol = TOL[prec]
     opts = hm.Options(precision=prec, scheme=hm.QE,
                       greeks=hm.GREEKS_PATHWISE | (hm.GREEKS_BUMP_FUSED if bumps else 0))
-    d = ctx.dump_paths(p.__dict__, opt_type, first + n, N, seed, first, n, opts).cpu().numpy()
-    rec, margin, amp = oracle.simulate_qe(p, opt_type, N, seed, first, n, threads=8)
+    d = ctx.dump_paths(p.__dict__, opt_type, n_total or first + n, N, seed, first, n,
+                       opts).cpu().numpy()
+    rec, margin, _ = oracle.simulate_qe(p, opt_type, N, seed, first, n, threads=8)
+    k = 14 if bumps else 6
+    ref = np.empty((n, k))
+    ref[:, :6] = rec
     skip = margin < MARGIN[prec]
-    vfloor = max(p.v0, p.theta)
-    X = rec[:, 2]
-    near = np.abs(X - p.K) < 1e3 * tol * p.K
-    floors = {"S_T": p.S0, "V_T": vfloor, "Sbar": p.S0, "pay": p.S0,
-              "pw_delta": 1.0, "pw_rho": p.K * p.T}
-    for k, name in enumerate(oracle.REC_FIELDS):
-        compare(name, d[:, k], rec[:, k], tol, floors[name],
-                skip | near if name in ("pw_delta", "pw_rho") else skip, amp)
+    base_skip = skip.copy()
     if bumps:
-        for k, (sc, q) in enumerate(list(oracle.scenario_params(p, oracle.Bumps()).items())[1:]):
-            r, m, a = oracle.simulate_qe(q, opt_type, N, seed, first, n, threads=8)
-            compare("pay_" + sc, d[:, 6 + k], r[:, 3], tol, p.S0, skip | (m < MARGIN[prec]), a)
+        for i, (_, q) in enumerate(list(oracle.scenario_params(p, oracle.Bumps()).items())[1:]):
+            r, m, _ = oracle.simulate_qe(q, opt_type, N, seed, first, n, threads=8)
+            ref[:, 6 + i] = r[:, 3]
+            skip |= m < MARGIN[prec]
     else:
         assert np.isnan(d[:, 6:14]).all()
+    vfloor = max(p.v0, p.theta)
+    floors = np.array([p.S0, vfloor, p.S0, p.S0, 1.0, p.K * p.T] + [p.S0] * 8)[:k]
+    bar = tol * np.maximum(np.abs(ref), floors)
+    if prec == 1:
+        bar = np.maximum(bar, 3 * qe_binary32.spread(p, opt_type, N, seed, first, n, ref, bumps,
+                                                      members=16))
+    near = np.abs(ref[:, 2] - p.K) < 1e3 * tol * p.K
+    names = list(oracle.REC_FIELDS) + ["pay_" + sc for sc in oracle.SCENARIOS[1:]]
+    for c in range(k):
+        sk = (base_skip if c < 6 else skip) | (near if names[c] in ("pw_delta", "pw_rho") else False)
+        compare(names[c], d[:, c], ref[:, c], bar[:, c], sk)
     assert skip.mean() < 0.01, f"{skip.mean():.3%} of paths near a branch decision"
     return d, rec
 
@@ -101,6 +115,28 @@ def test_qe_fp64_parity(hm, ctx, p, opt_type):
 def test_qe_fp32_parity(hm, ctx, p):
     for t in (0, 2, 4):
         check(hm, ctx, p, t, 4099, 24, 7, 1)
+
+
+def test_qe_fp32_full_size_sampled_and_reduction(hm, ctx):
+    """The 2^20-path x 252-step FP32 Asian call under QE with five bump Greeks,
+    in the launch the benchmark times: sampled windows against the oracle
+    (every column, the same bar as above), and the reduced estimates against
+    the host sums of every path's dumped record."""
+    n, N, seed = 1 << 20, 252, 42
+    opts = hm.Options(precision=hm.FP32, scheme=hm.QE)
+    r = ctx.price_greeks(PB.__dict__, hm.ASIAN_CALL, n, N, seed, opts)
+    full = ctx.dump_paths(PB.__dict__, hm.ASIAN_CALL, n, N, seed, 0, n, opts).cpu().numpy()
+    for first in (0, n // 2 + 12345, n - 512):
+        d, _ = check(hm, ctx, PB, hm.ASIAN_CALL, 512, N, seed, 1, first=first, n_total=n)
+        np.testing.assert_array_equal(d, full[first:first + 512])
+    pay = {sc: full[:, 6 + k] for k, sc in enumerate(oracle.SCENARIOS[1:])}
+    pay["base"] = full[:, 3]
+    samples = oracle.greek_samples(pay, PB)
+    samples["pw_delta"], samples["pw_rho"] = full[:, 4], full[:, 5]
+    for k, y in samples.items():
+        m, se = oracle.mean_se(y)
+        assert r[k][0] == pytest.approx(m, rel=1e-9, abs=1e-12), k
+        assert r[k][1] == pytest.approx(se, rel=1e-6), k
 
 
 def test_qe_exponential_branch_is_exercised(hm, ctx):
