@@ -13,6 +13,8 @@ import numpy as np
 import pytest
 
 import oracle
+import tangent_spread
+import workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +67,10 @@ def test_alone_and_in_the_mix(hm, ctx, want):
     reqs = requests(24, want=want)
     mix, stats = serve(hm, ctx, reqs, precision=hm.FP32)
     assert stats["completed"] == 24 and stats["p50_ms"] > 0 and stats["p99_ms"] >= stats["p50_ms"]
+    # latency: submit to completion; device time: the launches that carried its items
+    lat = np.array([r["latency_ms"] for r in mix])
+    assert (lat > 0).all() and stats["p50_ms"] == pytest.approx(np.percentile(lat, 50), rel=0.05)
+    assert all(0 < r["device_ms"] <= r["latency_ms"] for r in mix)
     for i in (0, 5, 17):
         alone, _ = serve(hm, ctx, [reqs[i]], precision=hm.FP32)
         for k in ("price", "pw_delta", "pw_rho", "adj", "n_paths"):
@@ -84,6 +90,33 @@ def test_served_fp64_matches_batch_and_oracle(hm, ctx):
         m, se = oracle.mean_se(rec[:, 3])
         assert r["price"][0] == pytest.approx(m, rel=1e-10, abs=1e-12)
         assert r["price"][1] == pytest.approx(se, rel=1e-6)
+
+
+def test_served_fp32_adjoint_matches_oracle(hm, ctx):
+    """Served requests in the serving workload's mode (FP32, adjoint
+    sensitivities, 50..1000 steps, Heston parameters of the request stream)
+    against the oracle's forward-mode derivatives on the same paths, with the
+    mean-level bars of the batch tests: per path max(1e-5 max(|o|, floor)
+    max(1, a_p), 3 x the binary32 rounding spread of the oracle's
+    derivatives), summed over paths / n."""
+    rs = workloads.request_stream(6, 1.0, seed=21)
+    reqs = [dict(params=rs.params[i], type=int(rs.opt_type[i]), n_steps=int(rs.n_steps[i]),
+                 n_paths=2048 + 999 * i, seed=int(rs.seed[i]), want=2) for i in range(6)]
+    assert max(q["n_steps"] for q in reqs) > 300
+    res, _ = serve(hm, ctx, reqs, precision=hm.FP32)
+    for q, r in zip(reqs, res):
+        assert r["n_paths"] == q["n_paths"]
+        p = oracle.Params(**q["params"])
+        tan, s = tangent_spread.spread(p, q["type"], q["n_steps"], q["seed"], 0, q["n_paths"], 1)
+        amp = np.maximum(1.0, tan[:, 8])
+        f = np.array([p.S0, 1.0, p.S0, p.K * p.T, p.S0 * p.T, p.S0 * p.T, p.S0, p.S0])
+        per = np.maximum(1e-5 * np.maximum(np.abs(tan[:, :8]), f) * amp[:, None], 3 * s)
+        per[:, 0] = 1e-5 * np.maximum(np.abs(tan[:, 0]), p.S0)
+        bar = per.mean(axis=0)
+        m = tan[:, :8].mean(axis=0)
+        assert abs(r["price"][0] - m[0]) <= bar[0], q
+        for k in range(7):
+            assert abs(r["adj"][k][0] - m[1 + k]) <= bar[1 + k], (q, k, r["adj"][k], m[1 + k])
 
 
 def test_se_target_stops_at_first_item_boundary(hm, ctx):

@@ -107,15 +107,15 @@ class Portfolio:
                             "n_steps", "opt_type", "seed")), S0=self.S0, r=self.r)
 
 
-def portfolio(n: int = 4096, seed: int = 3, log2_paths=(14, 20)) -> Portfolio:
+def portfolio(n: int = 4096, seed: int = 3, paths=(1 << 14, 1 << 20)) -> Portfolio:
     """Draws in column order from numpy PCG64(seed): K~U[70,130], T~U[0.1,5],
-    paths = 2^U{lo..hi}, kappa~U[.5,4], theta~U[.01,.09], sigma~U[.1,.8],
-    rho~U[-.9,0], v0~U[.01,.09]; steps = ceil(252 T); type = i mod 4;
-    per-option seed 42 + (i << 32)."""
+    paths ~ U{lo..hi} (integers, uniform), kappa~U[.5,4], theta~U[.01,.09],
+    sigma~U[.1,.8], rho~U[-.9,0], v0~U[.01,.09]; steps = ceil(252 T);
+    type = i mod 4; per-option seed 42 + (i << 32)."""
     g = np.random.Generator(np.random.PCG64(seed))
     K = g.uniform(70.0, 130.0, n)
     T = g.uniform(0.1, 5.0, n)
-    lp = g.integers(log2_paths[0], log2_paths[1] + 1, n)
+    npaths = g.integers(paths[0], paths[1] + 1, n)
     kappa = g.uniform(0.5, 4.0, n)
     theta = g.uniform(0.01, 0.09, n)
     sigma = g.uniform(0.1, 0.8, n)
@@ -123,7 +123,7 @@ def portfolio(n: int = 4096, seed: int = 3, log2_paths=(14, 20)) -> Portfolio:
     v0 = g.uniform(0.01, 0.09, n)
     steps = np.ceil(252.0 * T).astype(np.int64)
     idx = np.arange(n, dtype=np.uint64)
-    return Portfolio(K, T, (np.int64(1) << lp).astype(np.int64), kappa, theta, sigma, rho, v0,
+    return Portfolio(K, T, npaths.astype(np.int64), kappa, theta, sigma, rho, v0,
                      steps, (idx % 4).astype(np.int32), (np.uint64(42) + (idx << np.uint64(32))))
 
 
