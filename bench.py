@@ -230,7 +230,7 @@ def serving(ctx, hm, torch, n_measured=1000, n_warm=100):
     for frac in (0.5, 0.8):
         rs = request_stream(n_warm + n_measured, frac * mu, seed=6)
         res, wall, st = run(to_reqs(rs), rs.arrival_s)
-        lat = np.array([r["device_ms"] for r in res[n_warm:]])
+        lat = np.array([r["latency_ms"] for r in res[n_warm:]])
         out[f"load_{frac}"] = {
             "arrival_rate_per_s": frac * mu, "requests": n_measured,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define HESTON_ABI_VERSION 2
+#define HESTON_ABI_VERSION 3
 
 /* Model and contract inputs (paper: Table "Heston model parameters"). */
 typedef struct heston_params {
@@ -167,10 +167,16 @@ typedef struct heston_result {
     uint64_t n_paths;  /* paths the estimates use                                            */
     uint32_t valid_mask;
     uint32_t reserved;
-    double device_ms; /* GPU time of the path kernel, HIP events on the context stream */
+    double device_ms; /* GPU time (HIP events): the path kernel of a pricing call, the
+                         batched launch of a batch; for a served request the summed
+                         durations of the launches that carried its work items (those
+                         launches also carry other requests' items)                   */
     heston_est cv_price; /* price with the control variate (HESTON_VALID_CONTROL)       */
     double cv_beta;      /* fitted control coefficient beta                             */
     double cv_mean;      /* E of the discounted control payoff, computed on the device  */
+    double latency_ms;   /* host wall time until the result was available: from entry
+                            to return of a synchronous call (pricing, batch), from
+                            heston_submit to completion of a served request            */
 } heston_result;
 
 typedef struct heston_opts {

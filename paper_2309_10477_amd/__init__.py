@@ -26,7 +26,7 @@ PHILOX, SOBOL_BRIDGE = 0, 1
  REFLECTION, EXACT) = 0, 1, 2, 3, 4, 5, 6, 7
 EXACT_MAX_STEPS = 4096
 GREEKS_PATHWISE, GREEKS_BUMP_FUSED, GREEKS_BUMP_PLAIN = 1, 2, 4
-ABI_VERSION = 2
+ABI_VERSION = 3
 CONTROL_NONE, CONTROL_GEOMETRIC = 0, 1
 CONTROL_MAX_FIXINGS = 8192
 VALID_PRICE, VALID_PATHWISE, VALID_BUMPS, VALID_ADJOINT, VALID_CONTROL = 1, 2, 4, 8, 16
@@ -57,7 +57,8 @@ class CResult(ctypes.Structure):
     _fields_ = [(n, CEst) for n in EST_NAMES] + [("adj", CEst * 7),
         ("n_paths", ctypes.c_uint64), ("valid_mask", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32), ("device_ms", ctypes.c_double),
-        ("cv_price", CEst), ("cv_beta", ctypes.c_double), ("cv_mean", ctypes.c_double)]
+        ("cv_price", CEst), ("cv_beta", ctypes.c_double), ("cv_mean", ctypes.c_double),
+        ("latency_ms", ctypes.c_double)]
 
 
 class COpts(ctypes.Structure):
@@ -255,7 +256,7 @@ class Context:
 
     def price_greeks(self, params, opt_type: int, n_paths: int, n_steps: int, seed: int,
                      opts: Options | None = None) -> dict:
-        """{estimator: (value, std_err)} plus 'device_ms' and 'n_paths'."""
+        """{estimator: (value, std_err)} plus 'device_ms', 'latency_ms' and 'n_paths'."""
         o = _OptsHolder(opts or Options(), n_steps)
         res = CResult()
         cp = _cparams(params)
@@ -360,6 +361,7 @@ def _result_dict(res: CResult) -> dict:
     out["valid_mask"] = res.valid_mask
     out["n_paths"] = res.n_paths
     out["device_ms"] = res.device_ms
+    out["latency_ms"] = res.latency_ms
     if res.valid_mask & VALID_CONTROL:
         out["cv_price"] = (res.cv_price.value, res.cv_price.std_err)
         out["cv_beta"] = res.cv_beta

@@ -3,6 +3,7 @@
 // context, kernel launches on the context's stream, and the final estimates.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -903,9 +904,10 @@ static heston_status run_exact(heston_ctx *c, const Request &q, uint64_t first, 
     return HESTON_OK;
 }
 
-heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
-                                     heston_option_type type, uint64_t n_paths, uint32_t n_steps,
-                                     uint64_t seed, const heston_opts *opts, heston_result *out)
+static heston_status price_greeks_impl(heston_ctx *c, const heston_params *params,
+                                       heston_option_type type, uint64_t n_paths,
+                                       uint32_t n_steps, uint64_t seed, const heston_opts *opts,
+                                       heston_result *out)
 {
     if (!c || !out)
         return fail(HESTON_INVALID_ARGUMENT, "ctx or out is NULL");
@@ -1025,6 +1027,18 @@ heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
     }
     *out = r;
     return HESTON_OK;
+}
+
+heston_status heston_price_greeks_ex(heston_ctx *c, const heston_params *params,
+                                     heston_option_type type, uint64_t n_paths, uint32_t n_steps,
+                                     uint64_t seed, const heston_opts *opts, heston_result *out)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const heston_status st = price_greeks_impl(c, params, type, n_paths, n_steps, seed, opts, out);
+    if (st == HESTON_OK)
+        out->latency_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return st;
 }
 
 heston_status heston_price_greeks(const heston_params *params, heston_option_type type,

@@ -1,6 +1,7 @@
 // heston_price_batch: the host side of the persistent batched kernel.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -200,6 +201,7 @@ extern "C" heston_status heston_price_batch(heston_ctx *c, const heston_request 
                                             const heston_opts *opts, heston_result *out,
                                             double *device_ms)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     if (!c || !reqs || !out || n == 0)
         return fail(HESTON_INVALID_ARGUMENT, "ctx, reqs or out is NULL, or n is 0");
     if (opts && opts->struct_size != sizeof(heston_opts))
@@ -252,6 +254,10 @@ extern "C" heston_status heston_price_batch(heston_ctx *c, const heston_request 
         fill_result(rq[i], rq[i].n_paths, &sums[(size_t)j * N_ACC], out[i]);
         out[i].device_ms = ms;
     }
+    const double wall =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (uint32_t i = 0; i < n; ++i)
+        out[i].latency_ms = wall;
     if (device_ms)
         *device_ms = ms;
     return HESTON_OK;

@@ -153,6 +153,7 @@ struct Req {
     uint32_t folded = 0;      // items folded (from the last completed launch)
     uint32_t target = 16;     // items the engine currently aims for
     uint32_t inflight = 0;    // launches holding items of this request
+    double gpu_ms = 0;        // summed durations of the completed launches that held its items
     bool done = false;
     unsigned char *mem = nullptr; // state then item records, in the pool
     ReqState *state() const { return reinterpret_cast<ReqState *>(mem); }
@@ -392,7 +393,8 @@ void finish(heston_server *s, Req *q, const ReqState &st)
     fill_result(q->r, n_used, st.sums, res);
     const double ms =
         std::chrono::duration<double, std::milli>(Clock::now() - q->t_submit).count();
-    res.device_ms = ms; // for served requests: the request's latency
+    res.device_ms = q->gpu_ms;
+    res.latency_ms = ms;
     s->results[q->ticket] = res;
     s->latencies_ms.push_back(ms);
     s->stats.completed++;
@@ -422,6 +424,7 @@ heston_status complete_ready(heston_server *s, bool block, bool &any)
             Req *q = L.reqs[j];
             const ReqState &st = L.h_out[j];
             q->inflight--;
+            q->gpu_ms += ms;
             if (!q->done) {
                 q->folded = st.folded;
                 if (st.done) {

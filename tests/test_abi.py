@@ -53,7 +53,8 @@ def test_struct_layout_matches_header():
            ' sizeof(heston_opts), sizeof(heston_result), offsetof(heston_opts, fixing_steps),'
            ' offsetof(heston_result, device_ms), offsetof(heston_opts, control_variate),'
            ' offsetof(heston_result, cv_mean), HESTON_CONTROL_GEOMETRIC, HESTON_VALID_CONTROL,'
-           ' HESTON_CONTROL_MAX_FIXINGS); return 0;}\n')
+           ' HESTON_CONTROL_MAX_FIXINGS); printf("%zu\\n", offsetof(heston_result, latency_ms));'
+           ' return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         open(c, "w").write(src)
@@ -63,7 +64,7 @@ def test_struct_layout_matches_header():
     want = [ctypes.sizeof(hm.CParams), ctypes.sizeof(hm.COpts), ctypes.sizeof(hm.CResult),
             hm.COpts.fixing_steps.offset, hm.CResult.device_ms.offset,
             hm.COpts.control_variate.offset, hm.CResult.cv_mean.offset, hm.CONTROL_GEOMETRIC,
-            hm.VALID_CONTROL, hm.CONTROL_MAX_FIXINGS]
+            hm.VALID_CONTROL, hm.CONTROL_MAX_FIXINGS, hm.CResult.latency_ms.offset]
     assert got == want
 
 
