@@ -1,15 +1,18 @@
 """GPU parity of the adjoint (reverse-mode) kernel and of plain bump-and-revalue.
 
-Per-path derivatives from heston_adjoint_backward against the oracle's
-forward-mode derivatives (which are pinned to finite differences in
-test_oracle.py), with |gpu - oracle| <= tol max(|oracle|, floor) max(1, a_p):
-floors 1 for d/dS0, S0 for d/dv0, d/dsigma and d/drho, K T for d/dr, S0 T for
-d/dkappa and d/dtheta; tol 1e-12 in FP64, 1e-5 in FP32.  a_p is the path's
-largest factor d sqrt(V+ dt)/dV+ = sqrt(dt/V+)/2 (reported by the oracle):
-both sweeps multiply by it where the variance nears zero, so it scales how
-far their different rounding orders can drift apart (observed: FP64
-differences up to 2.8e-11 relative on paths with a_p = 308; a_p has median
-~5 and 99th percentile ~50 at these parameters).  Payoffs keep the plain bar.
+Per-path payoffs and derivatives from heston_adjoint_backward against the
+oracle's forward-mode derivatives (which are pinned to finite differences in
+test_oracle.py): |gpu - oracle| <= max(tol max(|oracle|, floor), 4 x spread),
+tol 1e-12 in FP64 and 1e-5 in FP32; floors S0 for the payoff, d/dv0,
+d/dsigma and d/drho, 1 for d/dS0, K T for d/dr, S0 T for d/dkappa and
+d/dtheta.  The spread is how far Monte-Carlo-arithmetic evaluations of the
+same derivatives in the kernel's precision land from the oracle on that path
+(tests/tangent_binary32.py); it exceeds the plain bar only where the variance
+comes close to zero and the scheme amplifies rounding, and CPU tests
+(test_adjoint_conditioning.py) show both that no evaluation in that precision
+meets the plain bar there and that the bar covers independent evaluations.
+Paths whose averaged price lies within 1e3 tol K of the strike may switch the
+payoff indicator and are exempt.
 """
 import math
 
@@ -17,6 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
+import tangent_binary32 as tb
 from workloads import BASE, PAPER
 
 pytestmark = pytest.mark.gpu
@@ -55,22 +59,20 @@ def adjoint_per_path(hm, ctx, p, opt_type, n, N, seed, prec, every, scheme=0, fi
     return price, grads, pp.cpu().numpy()
 
 
-def check_against_tangent(d, p, opt_type, N, seed, first, n, prec, scheme, fixings, scale=1.0):
+def check_against_tangent(d, p, opt_type, N, seed, first, n, prec, scheme, fixings):
     tol = TOL[prec]
     mode = oracle.ABSORB if scheme == 1 else oracle.FULL_TRUNC
     tan = oracle.tangent(p, opt_type, N, seed, first, n, mode, fixings, threads=8)
     rec = oracle.simulate(p, opt_type, N, seed, first, n, mode, fixings, threads=8)
     near = np.abs(rec[:, 2] - p.K) < 1e3 * tol * p.K
-    amp = np.maximum(1.0, tan[:, 8])
-    floors = [p.S0, 1.0, p.S0, p.K * p.T, p.S0 * p.T, p.S0 * p.T, p.S0, p.S0]
+    bar = tb.bars(p, opt_type, N, seed, first, n, tan, mode, fixings,
+                  np.float64 if prec == 0 else np.float32)
     names = ["pay", "S0", "v0", "r", "kappa", "theta", "sigma", "rho"]
+    err = np.abs(d[:, :8] - tan[:, :8]) / bar
     for k in range(8):
-        o = tan[:, k] * (scale if k else 1.0)
-        g = d[:, k]
-        err = np.abs(g - o) / np.maximum(np.abs(o), floors[k]) / (amp if k else 1.0)
-        bad = (err > tol) & ~near
-        assert not bad.any(), (names[k], int(bad.sum()), float(err[bad].max()),
-                               int(np.argmax(np.where(bad, err, 0))))
+        bad = (err[:, k] > 1.0) & ~near
+        assert not bad.any(), (names[k], int(bad.sum()), float(err[bad, k].max()),
+                               int(np.argmax(np.where(bad, err[:, k], 0))))
 
 
 @pytest.mark.parametrize("opt_type", [0, 1, 2, 3])
@@ -96,24 +98,12 @@ def test_adjoint_fp32_matches_tangent(hm, ctx, every, opt_type):
 
 
 def test_adjoint_fp32_feller_violated_matches_tangent(hm, ctx):
-    """FP32 at vol of vol 0.6 (Feller violated; a_p up to ~300): per path
-    within max(1e-5 max(|o|, floor) max(1, a_p), 3 x the binary32 rounding
-    spread of the oracle's own derivatives, tests/tangent_spread.py); the
-    spread is what tests/test_adjoint_conditioning.py shows exceeds the
-    a_p-scaled bar where the variance touches zero."""
-    import tangent_spread
+    """FP32 at vol of vol 0.6 (Feller violated): the variance comes close to
+    zero on many paths, where the bar is set by the binary32 spread."""
     p, n, N, seed = PB.replace(sigma=0.6), 4096 + 100, 100, 5
     for opt_type in (0, 2):
         _, _, d = adjoint_per_path(hm, ctx, p, opt_type, n, N, seed, 1, 16)
-        tan, s = tangent_spread.spread(p, opt_type, N, seed, 0, n, 1)
-        rec = oracle.simulate(p, opt_type, N, seed, 0, n, threads=8)
-        near = np.abs(rec[:, 2] - p.K) < 1e3 * 1e-5 * p.K
-        amp = np.maximum(1.0, tan[:, 8])
-        floors = np.array([p.S0, 1.0, p.S0, p.K * p.T, p.S0 * p.T, p.S0 * p.T, p.S0, p.S0])
-        bar = np.maximum(1e-5 * np.maximum(np.abs(tan[:, :8]), floors) * amp[:, None], 3 * s)
-        bar[:, 0] = 1e-5 * np.maximum(np.abs(tan[:, 0]), p.S0)
-        bad = (np.abs(d - tan[:, :8]) > bar) & ~near[:, None]
-        assert not bad.any(), (opt_type, np.argwhere(bad)[:5])
+        check_against_tangent(d, p, opt_type, N, seed, 0, n, 1, 0, None)
 
 
 def test_adjoint_seed_gradient_scales(hm, ctx):

@@ -9,16 +9,18 @@ tests carried to the mean over the request's paths (sum of per-path bars / n):
 1e-5 max(|o|, floor) for prices; for the pathwise Delta and Rho also the jump
 of each path whose oracle average lies within ten times its own bar of the
 strike (there the binary32 average may fall on the other side and switch the
-indicator); for adjoint derivatives max(1e-5 max(|o|, floor) max(1, a_p),
-3 x the rounding spread of tests/tangent_spread.py), since where the
-variance touches zero binary32 rounding alone moves a path's derivatives
-further than the a_p-scaled bar (tests/test_adjoint_conditioning.py).
+indicator); for adjoint-mode payoffs and derivatives the per-path bars of the
+adjoint parity tests, max(tol max(|o|, floor), 4 x spread), the spread being
+how far Monte-Carlo-arithmetic evaluations in the kernel's precision land from
+the oracle on the path (tests/tangent_binary32.py): where the variance comes
+close to zero rounding alone moves a path's derivatives further than the
+plain bar (tests/test_adjoint_conditioning.py).
 """
 import numpy as np
 import pytest
 
 import oracle
-import tangent_spread
+import tangent_binary32 as tb
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -80,14 +82,12 @@ def fp32_bars(q, rec):
 
 
 def adjoint_bars(q, prec):
-    """Oracle tangent means [8] (price, 7 derivatives) and their mean-level bars."""
+    """Oracle tangent means [8] (price, 7 derivatives), their SEs and the
+    mean-level bars (per-path bars summed over the paths / n)."""
     p = oracle.Params(**q["params"])
-    tan, s = tangent_spread.spread(p, q["type"], q["n_steps"], q["seed"], 0, q["n_paths"], prec)
-    tol = 1e-12 if prec == 0 else 1e-5
-    amp = np.maximum(1.0, tan[:, 8])
-    f = np.array([p.S0, 1.0, p.S0, p.K * p.T, p.S0 * p.T, p.S0 * p.T, p.S0, p.S0])
-    per = np.maximum(tol * np.maximum(np.abs(tan[:, :8]), f) * amp[:, None], 3 * s)
-    per[:, 0] = tol * np.maximum(np.abs(tan[:, 0]), p.S0)
+    tan = oracle.tangent(p, q["type"], q["n_steps"], q["seed"], 0, q["n_paths"], threads=8)
+    per = tb.bars(p, q["type"], q["n_steps"], q["seed"], 0, q["n_paths"], tan,
+                  dtype=np.float64 if prec == 0 else np.float32)
     m, se = oracle.mean_se(tan[:, :8])
     return m, se, per.mean(axis=0)
 
@@ -178,7 +178,7 @@ def test_portfolio_4096_options(hm, ctx):
     """The 4096-option portfolio (K, T, paths 2^14..2^20, Heston parameters
     drawn per option; steps = ceil(252 T)) in one launch.  Checked against the
     oracle: the four options with the fewest path-steps, and the six
-    longest-maturity options among those with at most 2^15 paths that violate
+    longest-maturity options among those with at most 2^16 paths that violate
     the Feller condition (over a thousand FP32 steps each)."""
     pf = workloads.portfolio()
     reqs = [dict(params=pf.params(i), type=int(pf.opt_type[i]), n_steps=int(pf.n_steps[i]),
@@ -187,7 +187,7 @@ def test_portfolio_4096_options(hm, ctx):
     assert all(np.isfinite(r["price"][0]) and r["price"][1] >= 0 for r in res)
     cost = pf.n_paths * pf.n_steps
     feller = 2 * pf.kappa * pf.theta < pf.sigma ** 2
-    cand = np.nonzero((pf.n_paths <= 1 << 15) & feller)[0]
+    cand = np.nonzero((pf.n_paths <= 1 << 16) & feller)[0]
     long_ = cand[np.argsort(-pf.n_steps[cand])[:6]]
     assert len(long_) == 6 and pf.n_steps[long_].min() > 1000
     for i in list(np.argsort(cost)[:4]) + list(long_):

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-import tangent_spread
+import tangent_binary32 as tb
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -96,9 +96,9 @@ def test_served_fp32_adjoint_matches_oracle(hm, ctx):
     """Served requests in the serving workload's mode (FP32, adjoint
     sensitivities, 50..1000 steps, Heston parameters of the request stream)
     against the oracle's forward-mode derivatives on the same paths, with the
-    mean-level bars of the batch tests: per path max(1e-5 max(|o|, floor)
-    max(1, a_p), 3 x the binary32 rounding spread of the oracle's
-    derivatives), summed over paths / n."""
+    mean-level bars of the batch tests: per path max(1e-5 max(|o|, floor),
+    4 x the binary32 spread of tests/tangent_binary32.py), summed over the
+    paths / n."""
     rs = workloads.request_stream(6, 1.0, seed=21)
     reqs = [dict(params=rs.params[i], type=int(rs.opt_type[i]), n_steps=int(rs.n_steps[i]),
                  n_paths=2048 + 999 * i, seed=int(rs.seed[i]), want=2) for i in range(6)]
@@ -107,12 +107,8 @@ def test_served_fp32_adjoint_matches_oracle(hm, ctx):
     for q, r in zip(reqs, res):
         assert r["n_paths"] == q["n_paths"]
         p = oracle.Params(**q["params"])
-        tan, s = tangent_spread.spread(p, q["type"], q["n_steps"], q["seed"], 0, q["n_paths"], 1)
-        amp = np.maximum(1.0, tan[:, 8])
-        f = np.array([p.S0, 1.0, p.S0, p.K * p.T, p.S0 * p.T, p.S0 * p.T, p.S0, p.S0])
-        per = np.maximum(1e-5 * np.maximum(np.abs(tan[:, :8]), f) * amp[:, None], 3 * s)
-        per[:, 0] = 1e-5 * np.maximum(np.abs(tan[:, 0]), p.S0)
-        bar = per.mean(axis=0)
+        tan = oracle.tangent(p, q["type"], q["n_steps"], q["seed"], 0, q["n_paths"], threads=8)
+        bar = tb.bars(p, q["type"], q["n_steps"], q["seed"], 0, q["n_paths"], tan).mean(axis=0)
         m = tan[:, :8].mean(axis=0)
         assert abs(r["price"][0] - m[0]) <= bar[0], q
         for k in range(7):
