@@ -22,16 +22,17 @@ template <class R> __device__ __forceinline__ Coef<R> coef(const StepCoef &s)
 // sz2 = sigma Z2.  FT: full truncation (V+ in drift and diffusion, V carried);
 // otherwise absorption (V clamped at 0 after the step).  sdt is the time step
 // under the square root: dt, or dt NS^2 with scaled normals (NormalScale).
+// Returns the variance before the absorption clamp.
 template <class R, bool FT>
-__device__ __forceinline__ void mil_step(R &x, R &v, const Coef<R> &c, R z1, R sz2, R mil, R sdt)
+__device__ __forceinline__ R mil_step(R &x, R &v, const Coef<R> &c, R z1, R sz2, R mil, R sdt)
 {
     const R vp = v > R(0) ? v : R(0);
     const R s = fast_sqrt(vp * sdt);
     x += (c.r_dt - c.half_dt * vp) + s * z1;
     const R vb = FT ? v : vp;
-    v = vb + (c.ktdt - c.kdt * vp) + sz2 * s + mil;
-    if (!FT)
-        v = v > R(0) ? v : R(0);
+    const R pre = vb + (c.ktdt - c.kdt * vp) + sz2 * s + mil;
+    v = FT ? pre : (pre > R(0) ? pre : R(0));
+    return pre;
 }
 
 // Step j+1 is a fixing date (every step when the mask is absent).
@@ -225,12 +226,9 @@ __device__ __forceinline__ void adjoint_path(const PathConsts &k, uint64_t p, co
                         a_vp[qq] = vp;
                         a_za[qq] = za[h];
                         a_zb[qq] = zb[h];
-                        const R vb = FT ? v : vp;
-                        const R vpre = vb + (c.ktdt - c.kdt * vp) +
-                                       (ns.sigma * z2) * fast_sqrt(vp * ns.sdt) +
-                                       c.qdt * (z2 * z2 - R(1));
-                        mil_step<R, FT>(x, v, c, za[h], ns.sigma * z2, c.qdt * (z2 * z2 - R(1)),
-                                        ns.sdt);
+                        // the clip flag comes from the very value the step clamped
+                        const R vpre = mil_step<R, FT>(x, v, c, za[h], ns.sigma * z2,
+                                                       c.qdt * (z2 * z2 - R(1)), ns.sdt);
                         a_clip[qq] = !FT && !(vpre > R(0));
                         a_f[qq] = (ASIAN && is_fixing(k.fix_bits, s0 + qq + 1)) ? c_fix * fast_exp(x)
                                                                                : R(0);
