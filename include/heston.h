@@ -241,6 +241,29 @@ heston_status heston_price_greeks(const heston_params *params, heston_option_typ
                                   uint64_t n_paths, uint32_t n_steps, uint64_t seed,
                                   heston_result *out);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): heston_price_greeks_ex
+ * without a context and without any device or pinned-host allocation.  The
+ * call keeps its device scratch (fixing mask and weights, block partials,
+ * reduction sums) in one fixed array of HESTON_NOALLOC_SCRATCH_BYTES per
+ * device, held by the library until the process ends; the first call on a
+ * device looks up that array's address and creates two timing events.
+ * Kernels and copies run on `hip_stream` (a hipStream_t; NULL: the device's
+ * null stream) of the current HIP device, and the call blocks until the
+ * result is on the host.  Results are bitwise those of heston_price_greeks_ex
+ * with the same arguments.  Calls that overlap on one device share the array
+ * and race: serialise them.  Nothing in the array needs to start at zero.
+ * Covers Philox normals, every Milstein/Euler/QE scheme flag, European and
+ * Asian payoffs, pathwise Greeks and fused bumps.  Errors: INVALID_ARGUMENT,
+ * UNSUPPORTED (Sobol normals, exact simulation, plain bumps, control
+ * variate), OVER_BUDGET (the request's scratch exceeds the fixed size: about
+ * 0.5 byte per path plus 64 bytes per step), DEVICE_ERROR. */
+#define HESTON_NOALLOC_SCRATCH_BYTES (16u << 20)
+heston_status heston_price_greeks_noalloc(const heston_params *params, heston_option_type type,
+                                          uint64_t n_paths, uint32_t n_steps, uint64_t seed,
+                                          const heston_opts *opts, void *hip_stream,
+                                          heston_result *out);
+
 /* Per-path records of paths first .. first+count-1 of the same request, for
  * parity checks: writes count x HESTON_DUMP_WIDTH doubles, row-major, to the
  * DEVICE buffer `out_dev` (caller-owned, at least count*HESTON_DUMP_WIDTH*8

@@ -125,6 +125,8 @@ def lib():
                                          c.c_uint64, P(COpts), P(CResult)]
     L.heston_price_greeks.argtypes = [P(CParams), c.c_int, c.c_uint64, c.c_uint32, c.c_uint64,
                                       P(CResult)]
+    L.heston_price_greeks_noalloc.argtypes = [P(CParams), c.c_int, c.c_uint64, c.c_uint32,
+                                              c.c_uint64, P(COpts), c.c_void_p, P(CResult)]
     L.heston_dump_paths.argtypes = [c.c_void_p, P(CParams), c.c_int, c.c_uint64, c.c_uint32,
                                     c.c_uint64, P(COpts), c.c_uint64, c.c_uint64, c.c_void_p]
     L.heston_status_str.argtypes = [c.c_int]
@@ -375,6 +377,22 @@ def price_greeks(params, opt_type: int, n_paths: int, n_steps: int, seed: int) -
     cp = _cparams(params)
     check(lib().heston_price_greeks(ctypes.byref(cp), opt_type, n_paths, n_steps, seed,
                                     ctypes.byref(res)))
+    return _result_dict(res)
+
+
+def price_greeks_noalloc(params, opt_type: int, n_paths: int, n_steps: int, seed: int,
+                         opts: Options | None = None, stream=None) -> dict:
+    """heston_price_greeks_noalloc: no context and no allocation, on `stream`
+    (a torch stream or a hipStream_t address; None: the current device's null
+    stream)."""
+    o = _OptsHolder(opts or Options(), n_steps)
+    res = CResult()
+    cp = _cparams(params)
+    ptr = 0 if stream is None else (stream.cuda_stream if hasattr(stream, "cuda_stream")
+                                    else int(stream))
+    check(lib().heston_price_greeks_noalloc(ctypes.byref(cp), opt_type, n_paths, n_steps, seed,
+                                            ctypes.byref(o.c), ctypes.c_void_p(ptr),
+                                            ctypes.byref(res)))
     return _result_dict(res)
 
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -276,9 +277,10 @@ heston_status check_request(const Request &q)
     return HESTON_OK;
 }
 
-// Builds the launch description of paths [first, first+count) of request q
-// and uploads its tables.  Does not launch.
-heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t count, PriceLaunch &L)
+// The launch description of paths first .. first+count-1 of q from the request
+// alone: model, scheme, time grids, bump sizes and fixing counts.  Device
+// tables and buffers are left null.
+void plan_launch(const Request &q, uint64_t first, uint64_t count, PriceLaunch &L)
 {
     const heston_params &p = q.p;
     const heston_opts &o = q.o;
@@ -318,7 +320,6 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
             L.tup.quarter_sigma2_dt = L.tdn.quarter_sigma2_dt = 0.0;
     }
     const bool asian = q.type >= 2;
-    const bool geo = q.type == HESTON_GEO_ASIAN_CALL || q.type == HESTON_GEO_ASIAN_PUT;
     L.n_fix = asian ? (o.fixing_steps ? o.n_fixings : q.n_steps) : 1;
     // sum of the fixing step indices: the fixing times sum to dt times it
     L.fix_step_sum = 0.0;
@@ -327,6 +328,16 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
             L.fix_step_sum += (double)o.fixing_steps[i];
     else
         L.fix_step_sum = 0.5 * (double)q.n_steps * ((double)q.n_steps + 1.0);
+}
+
+// Builds the launch description of paths [first, first+count) of request q
+// and uploads its tables into the context's scratch.  Does not launch.
+heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t count, PriceLaunch &L)
+{
+    const heston_opts &o = q.o;
+    plan_launch(q, first, count, L);
+    const bool asian = q.type >= 2;
+    const bool geo = q.type == HESTON_GEO_ASIAN_CALL || q.type == HESTON_GEO_ASIAN_PUT;
     {
         heston_status st = upload_fix_bits(c, q, &L.fix_bits);
         if (st != HESTON_OK)
@@ -629,6 +640,66 @@ heston_status check_adjoint(const Request &q, uint32_t every, const void *ckpt, 
     if (bytes < need)
         return fail(HESTON_INVALID_ARGUMENT, "checkpoint buffer smaller than " +
                                                  std::to_string(need) + " bytes");
+    return HESTON_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of heston_price_greeks_noalloc: one array per device,
+// held until the process ends.  Host code never passes `scratch` itself (its
+// name is a host-side stand-in); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[HESTON_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+struct NoallocDevice {
+    unsigned char *ptr = nullptr; // device address of `scratch` on this device
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+static std::mutex g_noalloc_mu;
+static NoallocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+
+// Set-up on the current device (first call only): the scratch address and
+// the two timing events.
+static heston_status noalloc_device(int dev, NoallocDevice **out)
+{
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(HESTON_UNSUPPORTED, "device index above the no-allocation limit");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoallocDevice &d = g_noalloc[dev];
+    if (!d.ptr) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!d.ev0)
+            HIP_TRY(hipEventCreate(&d.ev0));
+        if (!d.ev1)
+            HIP_TRY(hipEventCreate(&d.ev1));
+        d.ptr = (unsigned char *)p;
+    }
+    *out = &d;
+    return HESTON_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// The fixing-date bitmask of q written to dev_bits (device, `words` words) in
+// chunks staged through a small host array.
+static heston_status noalloc_fix_bits(const Request &q, uint32_t *dev_bits, size_t words,
+                                      hipStream_t stream)
+{
+    constexpr size_t CH = 1024;
+    uint32_t chunk[CH];
+    uint32_t i = 0; // next fixing step (the steps are strictly increasing)
+    for (size_t w0 = 0; w0 < words; w0 += CH) {
+        const size_t n = std::min(CH, words - w0);
+        std::memset(chunk, 0, sizeof(chunk));
+        for (; i < q.o.n_fixings && q.o.fixing_steps[i] < 32 * (w0 + n); ++i) {
+            const uint32_t j = q.o.fixing_steps[i];
+            chunk[(j >> 5) - w0] |= 1u << (j & 31u);
+        }
+        HIP_TRY(hipMemcpyAsync(dev_bits + w0, chunk, n * 4, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream)); // `chunk` is refilled next
+    }
     return HESTON_OK;
 }
 
@@ -1188,6 +1259,100 @@ heston_status heston_adjoint_backward(heston_ctx *c, const heston_params *params
         grads[k] = est_from((double)n_paths, c->host_sums[2 * (k + 1)], c->host_sums[2 * (k + 1) + 1]);
     if (device_ms)
         *device_ms = ms;
+    return HESTON_OK;
+}
+
+heston_status heston_price_greeks_noalloc(const heston_params *params, heston_option_type type,
+                                          uint64_t n_paths, uint32_t n_steps, uint64_t seed,
+                                          const heston_opts *opts, void *hip_stream,
+                                          heston_result *out)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!out)
+        return fail(HESTON_INVALID_ARGUMENT, "out is NULL");
+    if (opts && opts->struct_size != sizeof(heston_opts))
+        return fail(HESTON_INVALID_ARGUMENT, "opts->struct_size does not match this library");
+    const Request q = make_request(params, type, n_paths, n_steps, seed, opts);
+    heston_status st = check_request(q);
+    if (st != HESTON_OK)
+        return st;
+    if (q.o.rng != HESTON_RNG_PHILOX)
+        return fail(HESTON_UNSUPPORTED, "the no-allocation call takes Philox normals only");
+    if (q.o.scheme == HESTON_EXACT)
+        return fail(HESTON_UNSUPPORTED, "the no-allocation call does not run exact simulation");
+    if (q.o.greeks & HESTON_GREEKS_BUMP_PLAIN)
+        return fail(HESTON_UNSUPPORTED, "the no-allocation call gives fused bumps only");
+    if (q.o.control_variate != HESTON_CONTROL_NONE)
+        return fail(HESTON_UNSUPPORTED, "the no-allocation call takes no control variate");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    NoallocDevice *d = nullptr;
+    if ((st = noalloc_device(dev, &d)) != HESTON_OK)
+        return st;
+    hipStream_t stream = (hipStream_t)hip_stream;
+
+    PriceLaunch L;
+    plan_launch(q, 0, n_paths, L);
+    L.rep0 = 0;
+    L.n_reps = 1;
+    L.paths_per_rep = n_paths;
+    L.blocks_per_rep = (uint32_t)std::min<uint64_t>((n_paths + BLOCK - 1) / BLOCK, 0xFFFFFFFFu);
+    // scratch layout: fixing bitmask, fixing weights, block partials,
+    // first-level sums, estimator sums (each 256-byte aligned)
+    const bool asian = q.type >= 2;
+    const bool geo = q.type == HESTON_GEO_ASIAN_CALL || q.type == HESTON_GEO_ASIAN_PUT;
+    const size_t W = (size_t)L.acc_width();
+    const size_t words = (asian && q.o.fixing_steps) ? (q.n_steps + 1 + 31) / 32 : 0;
+    const size_t weights =
+        (asian && !geo) ? (size_t)q.n_steps * STEP_WEIGHTS * (q.o.precision == HESTON_FP64 ? 8 : 4) : 0;
+    const size_t chunks = (L.blocks_per_rep + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
+    const size_t o_bits = 0, o_w = align256(o_bits + words * 4);
+    const size_t o_part = align256(o_w + weights);
+    const size_t o_tmp = align256(o_part + (size_t)L.blocks_per_rep * W * 8);
+    const size_t o_sums = align256(o_tmp + (chunks > 1 ? chunks * W * 8 : 0));
+    const size_t need = o_sums + W * 8;
+    if ((uint64_t)L.blocks_per_rep * BLOCK < n_paths || need > HESTON_NOALLOC_SCRATCH_BYTES)
+        return fail(HESTON_OVER_BUDGET,
+                    "the request needs " + std::to_string(need) +
+                        " bytes of device scratch, more than the no-allocation call's fixed " +
+                        std::to_string((size_t)HESTON_NOALLOC_SCRATCH_BYTES));
+    unsigned char *base = d->ptr;
+    if (words) {
+        if ((st = noalloc_fix_bits(q, (uint32_t *)(base + o_bits), words, stream)) != HESTON_OK)
+            return st;
+        L.fix_bits = (const uint32_t *)(base + o_bits);
+    }
+    if (weights) {
+        L.step_weights = base + o_w;
+        HIP_TRY(launch_step_weights(L, base + o_w, stream));
+    }
+    L.partials = (double *)(base + o_part);
+    L.reduce_tmp = chunks > 1 ? (double *)(base + o_tmp) : nullptr;
+    L.dump = nullptr;
+    double *dev_sums = (double *)(base + o_sums);
+    double sums[N_ACC];
+    HIP_TRY(hipEventRecord(d->ev0, stream));
+    HIP_TRY(launch_paths(L, stream));
+    HIP_TRY(hipEventRecord(d->ev1, stream));
+    HIP_TRY(launch_reduce(L, dev_sums, stream));
+    HIP_TRY(hipMemcpyAsync(sums, dev_sums, W * 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, d->ev0, d->ev1));
+
+    heston_result r;
+    std::memset(&r, 0, sizeof(r));
+    heston_est *slot[N_EST] = {&r.price, &r.pw_delta, &r.pw_rho, &r.delta,
+                               &r.gamma, &r.vega,     &r.rho,    &r.theta};
+    const int n_est = L.bumps ? N_EST : EST_DELTA;
+    for (int e = 0; e < n_est; ++e)
+        *slot[e] = est_from((double)n_paths, sums[2 * e], sums[2 * e + 1]);
+    r.n_paths = n_paths;
+    r.valid_mask = HESTON_VALID_PRICE | HESTON_VALID_PATHWISE | (L.bumps ? HESTON_VALID_BUMPS : 0u);
+    r.device_ms = ms;
+    r.latency_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = r;
     return HESTON_OK;
 }
 
