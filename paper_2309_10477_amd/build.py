@@ -21,7 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ("api.hip", "price_kernel.hip", "adjoint_kernel.hip", "batch_kernel.hip",
            "batch_api.hip", "server.hip", "geo_control.hip", "exact_kernel.hip")
 SRC = [os.path.join(HERE, "csrc", f) for f in SOURCES]
-HDRS = [os.path.join(HERE, "csrc", f) for f in ("internal.hpp", "device_math.hpp", "cplx.hpp",
+HDRS = [os.path.join(HERE, "csrc", f) for f in ("internal.hpp", "device_math.hpp",
+                                                "inv_normal_coef.hpp", "cplx.hpp",
                                                 "path_step.hpp", "runtime.hpp",
                                                 "batch_plan.hpp", "admission.hpp")] + \
     [os.path.join(os.path.dirname(HERE), "include", "heston.h")]

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "inv_normal_coef.hpp"
+
 namespace heston {
 
 // ---------------------------------------------------------------------------
@@ -83,30 +85,52 @@ __device__ __forceinline__ void box_muller(double ua, double ub, double &za, dou
     zb = rad * s;
 }
 
-// Inverse standard normal CDF on the lower half, u in [2^-31, 1/2].
-// Single precision: Wichura's algorithm AS 241 (Applied Statistics 37, 1988),
-// its single-precision form PPND7 (relative accuracy about 1e-7), evaluated
-// branch-free: the central rational in r = 0.180625 - q^2, q = u - 1/2, for
-// u >= 0.075 and the first tail rational in t = sqrt(-ln u) - 1.6 below: both
-// polynomials computed, numerator and denominator selected, one reciprocal.
-// All coefficients are positive and r, t >= 0 on their ranges, so neither
-// polynomial cancels in binary32.  The second tail
-// (sqrt(-ln u) > 5, u < 1.4e-11) lies outside the stated domain.
-// Double precision: the device math library's normcdfinv.
-__device__ __forceinline__ float inv_normal_lower(float u)
+// Inverse standard normal CDF on the lower half.
+// Single precision, from 30-bit coordinates: xs in [0, 2^29) stands for
+// u = (xs + 1/2) 2^-30.  In the erfinv variable of Giles (2011), w =
+// -ln(4u(1-u)), Phi^{-1}(u) = -(1 - 2u) Q(w) with Q smooth: a degree-10
+// polynomial in w - 4 for w <= 8 and a degree-7 polynomial in sqrt(w) - 3.6
+// beyond (u < 8.4e-5, down to 2^-31), both fitted to relative error 2.1e-7
+// in binary32 (coefficients and their fit: inv_normal_coef.hpp).  One
+// logarithm per normal.  2u = (2 xs + 1) 2^-30 is exact in binary32 after
+// rounding the integer, and 4u(1-u) = 2u (2 - 2u) keeps full relative
+// precision as u -> 0.
+template <int K>
+__device__ __forceinline__ float horner(const float (&c)[K], float t)
 {
-    const float q = u - 0.5f, r = 0.180625f - q * q;
-    const float num_c = ((59.109374720f * r + 159.29113202f) * r + 50.434271938f) * r + 3.3871327179f;
-    const float den_c = ((67.187563600f * r + 78.757757664f) * r + 17.895169469f) * r + 1.0f;
-    // -ln u = -ln2 log2 u
-    const float t =
-        __builtin_amdgcn_sqrtf(-0.69314718055994530942f * __builtin_amdgcn_logf(u)) - 1.6f;
-    const float num_t = ((0.17023821103f * t + 1.3067284816f) * t + 2.7568153900f) * t + 1.4234372777f;
-    const float den_t = (0.12021132975f * t + 0.73700164250f) * t + 1.0f;
-    // one reciprocal, of the selected denominator
-    const bool tail = u < 0.075f;
-    return (tail ? -num_t : q * num_c) * __builtin_amdgcn_rcpf(tail ? den_t : den_c);
+    float q = c[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k)
+        q = q * t + c[k];
+    return q;
 }
+
+// Two normals at once (the two coordinates of a bridge node): one branch
+// into the tail piece for both, which a wave takes only when one of its lanes
+// needs it for either.
+__device__ __forceinline__ void inv_normal_lower_bits2(uint32_t xa, uint32_t xb, float &za,
+                                                       float &zb)
+{
+    constexpr float LN2F = 0.69314718055994530942f;
+    const float a0 = (float)(2u * xa + 1u) * 0x1p-30f, a1 = (float)(2u * xb + 1u) * 0x1p-30f; // 2u
+    const float l0 = __builtin_amdgcn_logf(a0 * (2.0f - a0)); // log2(4u(1-u)) <= 0
+    const float l1 = __builtin_amdgcn_logf(a1 * (2.0f - a1));
+    float q0 = horner(INV_NORMAL_CENTRAL, l0 * -LN2F - INV_NORMAL_CENTER);
+    float q1 = horner(INV_NORMAL_CENTRAL, l1 * -LN2F - INV_NORMAL_CENTER);
+    constexpr float SPLIT = -INV_NORMAL_W_SPLIT / LN2F;
+    const bool t0 = l0 < SPLIT, t1 = l1 < SPLIT;
+    if (t0 || t1) {
+        const float p0 = horner(INV_NORMAL_TAIL,
+                                __builtin_amdgcn_sqrtf(l0 * -LN2F) - INV_NORMAL_TAIL_CENTER);
+        const float p1 = horner(INV_NORMAL_TAIL,
+                                __builtin_amdgcn_sqrtf(l1 * -LN2F) - INV_NORMAL_TAIL_CENTER);
+        q0 = t0 ? p0 : q0;
+        q1 = t1 ? p1 : q1;
+    }
+    za = (a0 - 1.0f) * q0; // -(1 - 2u) Q
+    zb = (a1 - 1.0f) * q1;
+}
+// Double precision, from u in (0, 1/2]: the device math library's normcdfinv.
 __device__ __forceinline__ double inv_normal_lower(double u) { return normcdfinv(u); }
 
 // Real-typed helpers.

@@ -52,21 +52,28 @@ __device__ __forceinline__ uint32_t sobol_coord(const uint32_t *__restrict__ dir
 // Standard normal of the 30-bit coordinate x, u = (x + 1/2) 2^-30.  The upper
 // half is mapped through its exact complement, z = -Phi^{-1}(1 - u), so that
 // single precision keeps full relative precision in both tails.
-template <class R> __device__ __forceinline__ R sobol_normal(uint32_t x)
+template <class R>
+__device__ __forceinline__ void sobol_normals(uint32_t x0, uint32_t x1, R &z0, R &z1)
 {
     if constexpr (sizeof(R) == 4) {
         // bit 29 marks the upper half: m is all ones there, and the mirror
         // 0x3FFFFFFF - x of a 30-bit x is x with its 30 bits complemented;
         // the sign is restored by flipping the float's sign bit (no selects)
-        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)x, 29, 1);
-        const uint32_t xs = x ^ (m & 0x3FFFFFFFu);
-        const float z = inv_normal_lower(((float)xs + 0.5f) * 0x1p-30f);
-        return __uint_as_float(__float_as_uint(z) ^ (m & 0x80000000u));
+        const uint32_t m0 = (uint32_t)__builtin_amdgcn_sbfe((int)x0, 29, 1);
+        const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)x1, 29, 1);
+        float a, b;
+        inv_normal_lower_bits2(x0 ^ (m0 & 0x3FFFFFFFu), x1 ^ (m1 & 0x3FFFFFFFu), a, b);
+        z0 = __uint_as_float(__float_as_uint(a) ^ (m0 & 0x80000000u));
+        z1 = __uint_as_float(__float_as_uint(b) ^ (m1 & 0x80000000u));
     } else {
-        const bool upper = x >= (1u << 29);
-        const uint32_t xs = upper ? 0x3FFFFFFFu - x : x;
-        const R z = inv_normal_lower(((R)xs + R(0.5)) * R(0x1p-30));
-        return upper ? -z : z;
+        auto one = [](uint32_t x) {
+            const bool upper = x >= (1u << 29);
+            const uint32_t xs = upper ? 0x3FFFFFFFu - x : x;
+            const R z = inv_normal_lower(((R)xs + R(0.5)) * R(0x1p-30));
+            return upper ? -z : z;
+        };
+        z0 = one(x0);
+        z1 = one(x1);
     }
 }
 
@@ -493,12 +500,11 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
                 if constexpr (FAST) {
                     const uint32_t *v6 = L.sobol_dir12 + 12u * pos;
                     const uint32_t c = 2u * pos;
-                    wa = sobol_normal<R>(shift[c] ^ hi_row[c] ^ sobol_low(v6, m));
-                    wb = sobol_normal<R>(shift[c + 1] ^ hi_row[c + 1] ^ sobol_low(v6 + 6, m));
+                    sobol_normals<R>(shift[c] ^ hi_row[c] ^ sobol_low(v6, m),
+                                     shift[c + 1] ^ hi_row[c + 1] ^ sobol_low(v6 + 6, m), wa, wb);
                 } else {
                     const uint32_t d = 2u * (uint32_t)k;
-                    wa = sobol_normal<R>(coord(d));
-                    wb = sobol_normal<R>(coord(d + 1));
+                    sobol_normals<R>(coord(d), coord(d + 1), wa, wb);
                 }
             };
             R ca = 0, cbm = 0; // B_j of the two motions
