@@ -61,8 +61,18 @@ __device__ __forceinline__ void run_item_paths(const BatchOption &op, uint64_t c
     }
 }
 
+// Adjoint items run the forward pass and the reverse sweep back to back, and
+// the single-precision kernel would hold 141 VGPRs (three waves per SIMD);
+// bounded to four waves per SIMD (128 VGPRs) the compiler spills a few
+// per-item values, reloaded once per item or sub-block, never inside the step
+// loops.
+template <class R, bool ADJ> struct BatchWaves {
+    static constexpr int value = (ADJ && sizeof(R) == 4) ? 4 : 1;
+};
+
 template <class R, bool FT, bool ADJ>
-__global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchOption *__restrict__ opts,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BatchWaves<R, ADJ>::value)))
+void batch_kernel(const BatchOption *__restrict__ opts,
                                                       const uint32_t *__restrict__ item_opt,
                                                       uint32_t item_begin, uint32_t item_end,
                                                       uint32_t *counter,
