@@ -8,12 +8,13 @@ all estimators reduced across paths and copied to the host.  Inputs are
 parameters only (nothing to stage); the timed region covers the library call.
 
 Prints ONE JSON line (rank 0).  Also reported: the roofline of the path kernel
-(an operation count per path-step against the FP32 vector peak), the Sobol +
-Brownian-bridge variant of the same step, the same step under the
-quadratic-exponential scheme, the same step with the geometric-average control
-variate, exact (Broadie-Kaya) simulation, the adjoint against plain bump-and-revalue, the 4096-option batch,
-the serving loop's latency, and the
-CPU oracle timed on a bounded sample of the same workload.
+(algorithmic FP32 FLOP per path-step against the FP32 vector peak, with the
+VALU utilisation of a counter pass), the latency of the small FP64 European
+call, the Sobol + Brownian-bridge variant of the same step, the same step
+under the quadratic-exponential scheme, the same step with the
+geometric-average control variate, exact (Broadie-Kaya) simulation, the
+adjoint against plain bump-and-revalue, the 4096-option batch, the serving
+loop's latency, and the CPU oracle timed on bounded samples of the workloads.
 """
 from __future__ import annotations
 
@@ -32,25 +33,35 @@ from workloads import ASIAN_LARGE, BASE, QMC_REPLICATES  # noqa: E402
 
 METRIC = "path-steps/s incl. Greeks, adjoint vs bump-revalue; p50/p99 request latency"
 
-# Vector-ALU operations per path-step of the dominant kernel (FP32, Philox,
-# Asian with a fixing every step, fused bumps = 5 path states, full
-# truncation), counted from the method's arithmetic as this kernel formulates
-# it, one per elementary lane operation (FMA, transcendental, 32x32->64
-# multiply, two-input XOR, shift, compare/select each count 1): Philox half
-# block 30, two uniforms 6, Box-Muller 7, correlation and the per-grid
-# Milstein coefficients 10, five state updates 5 x 7, fixing exponentials and
-# weighted sums 5 + 7.
-OPS_PER_PATH_STEP = 100.0
-# Published FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-operations/s
-# (256 CUs x 128 lanes/clk x 2.4 GHz); every counted operation is priced as one
-# such lane-operation.
-ALU_PEAK_OPS = 256 * 128 * 2.4e9
+# Algorithmic FP32 work per path-step of the dominant kernel (Philox, Asian
+# with a fixing every step, fused bumps = five path states: base, v0 +/-,
+# T +/-; full truncation), on the per-part basis of the method's operation
+# count, FMA = 2 FLOP, a transcendental = 1: shared by the five states, two
+# uniforms 4, Box-Muller 3 and the correlation 3; per state, the log-price
+# step 6, the variance step 9 and the daily fixing 7.  The S0 and r scenarios
+# are evaluated from the base state and add no per-step work.
+FLOP_PER_PATH_STEP = 10 + 5 * 22
+# Published FP32 vector peak of the MI355X: 256 CUs x 2.4 GHz x 256 FLOP per
+# clock (packed FP32 FMA).
+FP32_VECTOR_PEAK = 157.3e12
 # HBM bytes per launch of the path kernel from the FETCH_SIZE / WRITE_SIZE
 # counter passes (FETCH_SIZE scaled by 2.00 and WRITE_SIZE by 1.00, the factors
 # a 256 MiB device copy reads under the same counters); see
 # profiles/price_kernel_asian_2p20x252_fp32_bumps_hbm_counters.md.  Set to None
 # whenever the kernel changes until the counters are taken again.
 TRAFFIC_BYTES_PER_LAUNCH = 838_265
+# VALU utilisation of the path kernel from SQ counter passes of the same
+# build: the fraction of SIMD quad-cycles that issue a VALU instruction, the
+# share of lanes active in them, and the FLOP the hardware counted; see
+# profiles/valu_utilisation_counters.md.  Set to None whenever the kernel
+# changes until the counters are taken again.
+VALU_COUNTERS = {
+    "simd_valu_busy": 0.948,        # (SQ_ACTIVE_INST_VALU - SQ_ACTIVE_INST_VALU2) / SIMD quad-cycles
+    "valu_lane_util": 0.9994,       # SQ_THREAD_CYCLES_VALU / (SQ_ACTIVE_INST_VALU x 64)
+    "valu_utilisation": 0.947,      # their product: the path kernel's share of VALU issue capacity
+    "valubusy_amd_formula": 1.188,  # VALUBusy as rocprof defines it (counts dual-issued quad-cycles twice)
+    "counted_flop_per_path_step": 112.9,  # 64 x (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS + FP64 + _TRANS) / path-steps
+}
 
 
 def parse():
@@ -60,19 +71,24 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="qmc,qe,cv,exact,adjoint,batch,serve",
-                    help="extra legs reported after the timed steps: qmc, qe, cv, exact, adjoint, batch, "
-                         "serve, "
+    ap.add_argument("--legs", default="c1,qmc,qe,cv,exact,adjoint,batch,serve",
+                    help="extra legs reported after the timed steps: c1, qmc, qe, cv, exact, adjoint, "
+                         "batch, serve, "
                          "and copy (a 256 MiB device copy that calibrates HBM byte counters)")
     return ap.parse_args()
 
 
 def cpu_threads() -> int:
+    """Host threads for the oracle: the process's affinity set, bounded by the
+    CPU share the launcher grants (OMP_NUM_THREADS, when set)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    if share.isdigit() and int(share) > 0:
+        n = min(n, int(share))
+    return max(1, n)
 
 
 def cpu_baseline(target_s: float):
@@ -94,6 +110,78 @@ def cpu_baseline(target_s: float):
             "kind": "oracle",
             "sample": f"first {n} of {wl.n_paths} paths x {wl.n_steps} steps, 9 scenarios "
                       f"re-simulated in FP64 ({dt:.1f} s)"}
+
+
+def cpu_oracle_legs():
+    """The oracle timed on the other workloads, each on a bounded sample:
+    the 1e4 x 100 FP64 European call with its 9 bump scenarios in full; a
+    64-option subsample of the 4096-option portfolio (every 64th option, its
+    first 2048 paths); the finite-difference reference of the seven adjoint
+    sensitivities (15 revaluations) on the first 2^16 paths of the 2^22 x 365
+    European call.  Rates are base-scenario path-steps per second."""
+    import oracle
+    from workloads import ADJOINT_LARGE, EURO_SMALL, portfolio
+    threads = cpu_threads()
+    out = {"cores": threads, "kind": "oracle"}
+    wl = EURO_SMALL
+    p = oracle.Params(**wl.params)
+    t0 = time.perf_counter()
+    oracle.price_greeks(p, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, threads=threads)
+    dt = time.perf_counter() - t0
+    out["euro_call_1e4x100_fp64_bumps"] = {"latency_ms": dt * 1e3,
+                                           "path_steps_per_s": wl.n_paths * wl.n_steps / dt}
+    pf = portfolio()
+    idx = np.arange(0, len(pf), 64)
+    ps = 0
+    t0 = time.perf_counter()
+    for i in idx:
+        n = int(min(2048, pf.n_paths[i]))
+        oracle.simulate(oracle.Params(**pf.params(i)), int(pf.opt_type[i]), int(pf.n_steps[i]),
+                        int(pf.seed[i]), 0, n, threads=threads)
+        ps += n * int(pf.n_steps[i])
+    dt = time.perf_counter() - t0
+    out["portfolio_64_option_subsample"] = {
+        "path_steps_per_s": ps / dt, "path_steps": ps,
+        "extrapolated_portfolio_s": pf.path_steps() / (ps / dt),
+        "sample": f"options {idx[0]}, {idx[1]}, ..., {idx[-1]}: first min(2048, n) paths each"}
+    A = ADJOINT_LARGE
+    p = oracle.Params(**A["params"])
+    n, N = 1 << 16, A["n_steps"]
+    t0 = time.perf_counter()
+    oracle.simulate(p, 0, N, A["seed"], 0, n, threads=threads)
+    for name, _, rel, h in ADJ_BUMPS:
+        d = h * abs(getattr(p, name)) if rel else h
+        for sgn in (1.0, -1.0):
+            oracle.simulate(p.replace(**{name: getattr(p, name) + sgn * d}), 0, N, A["seed"], 0,
+                            n, threads=threads)
+    dt = time.perf_counter() - t0
+    out["adjoint_fd_reference_2p16x365"] = {
+        "path_steps_per_s": n * N / dt, "seconds": dt,
+        "sample": f"first {n} of {A['n_paths']} paths, 15 revaluations"}
+    return out
+
+
+def c1_latency(ctx, hm, torch, reps=200):
+    """The 1e4-path x 100-step FP64 European call with price, pathwise Delta/Rho
+    and the five central bump Greeks (fused kernel): p50/p99 latency of the
+    synchronous library call, results on the host."""
+    from workloads import EURO_SMALL as wl
+    opts = hm.Options(precision=hm.FP64)
+    for _ in range(10):
+        ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, opts)
+    torch.cuda.synchronize()
+    lat, dev = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, opts)
+        lat.append((time.perf_counter() - t0) * 1e3)
+        dev.append(r["device_ms"])
+    lat = np.array(lat)
+    return {"workload": wl.name, "calls": reps, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "kernel_ms_mean": float(np.mean(dev)),
+            "path_steps_per_s_at_p50": wl.n_paths * wl.n_steps / (np.percentile(lat, 50) * 1e-3),
+            "price": r["price"], "delta": r["delta"]}
 
 
 ADJ_BUMPS = (("S0", 0, 1, 0.01), ("v0", 4, 1, 0.01), ("r", 2, 0, 1e-4), ("kappa", 5, 1, 0.01),
@@ -192,7 +280,7 @@ def portfolio_batch(ctx, hm, torch):
             "path_steps_per_s": ps / wall, "kernel_path_steps_per_s": ps / (ms * 1e-3)}
 
 
-def serving(ctx, hm, torch, n_measured=1000, n_warm=100):
+def serving(ctx, hm, torch, n_measured=2000, n_warm=100):
     """Continuous batching: requests (50/50 European/Asian, calls/puts, path cap
     2^U[12,22], steps U{50..1000}, Heston parameters as the portfolio's, price
     + seven adjoint sensitivities to a price SE of 0.1) arrive as a Poisson
@@ -276,12 +364,16 @@ def main():
     value = path_steps / (wall / args.steps)
 
     k_ms = float(np.mean(kernel_ms))
-    achieved = OPS_PER_PATH_STEP * path_steps / (k_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-                "unit": "Top/s", "frac": achieved / ALU_PEAK_OPS,
+    achieved = FLOP_PER_PATH_STEP * path_steps / (k_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
                 "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+                "basis": f"algorithmic FP32 FLOP, {FLOP_PER_PATH_STEP} per path-step "
+                         "(FMA = 2, transcendental = 1), per launch / mean launch time",
                 "kernel": "price_kernel<float, Philox, Asian, fused bumps, full truncation>",
                 "kernel_ms": k_ms}
+    if VALU_COUNTERS is not None:
+        roofline["valu_counters"] = VALU_COUNTERS
 
     legs = set(a for a in args.legs.split(",") if a)
     out = {
@@ -297,6 +389,8 @@ def main():
         "estimates": {k: r[k] for k in ("price", "delta", "gamma", "vega", "rho", "theta",
                                         "pw_delta", "pw_rho")},
     }
+    if "c1" in legs:
+        out["euro_small_latency"] = c1_latency(ctx, hm, torch)
     if "qmc" in legs:
         # the same step with Sobol + Brownian-bridge normals (16 shifted replicates)
         qopts = hm.Options(precision=hm.FP32, rng=hm.SOBOL_BRIDGE, qmc_replicates=QMC_REPLICATES)
@@ -365,6 +459,7 @@ def main():
         out["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_oracle_legs"] = cpu_oracle_legs()
     ctx.close()
     print(json.dumps(out), flush=True)
 
