@@ -168,7 +168,10 @@ def tangent(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int = 
             n_paths: int = 1, mode: int = FULL_TRUNC, fixings=None, za=None, zb=None,
             threads: int = 1) -> np.ndarray:
     """Per-path [n_paths, 9] = (pay, d/dS0, d/dv0, d/dr, d/dkappa, d/dtheta, d/dsigma, d/drho,
-    max_j sqrt(dt / V+_j) / 2), the last the largest factor d sqrt(V+ dt)/dV+ on the path."""
+    c), with c the largest factor d sqrt(V+ dt)/dV+ = sqrt(dt / V+_j) / 2 on the path
+    (Milstein modes), or its smallest branch margin (QE: mode=QE, Philox inputs
+    only; the branch decisions are held fixed, so a bump smaller than the
+    margin does not move a branch)."""
     return _run("or_tangent", len(TAN_FIELDS), p, opt_type, n_steps, seed, first, n_paths, mode,
                 fixings, za, zb, threads)
 

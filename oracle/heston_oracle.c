@@ -25,7 +25,8 @@
  *     the exact derivative of the discrete average);
  *   - forward-mode (tangent) derivatives of each path's discounted payoff with
  *     respect to (S0, v0, r, kappa, theta, sigma, rho), by the chain rule
- *     carried step by step alongside the path;
+ *     carried step by step alongside the path, for the Milstein scheme and for
+ *     the QE scheme below (its branch decisions held fixed);
  *   - the paper's Euler discretisation (Background, "Euler discretisation"):
  *     the same log-price and variance steps without the Milstein term, with
  *     either truncation;
@@ -64,7 +65,8 @@
 
 #define OR_REC 6    /* S_T, V_T, Sbar, discounted payoff, pathwise Delta, pathwise Rho */
 #define OR_TAN 9    /* discounted payoff, d/dS0, d/dv0, d/dr, d/dkappa, d/dtheta, d/dsigma, d/drho,
-                       then the path's largest d sqrt(V+ dt) / dV+ = max_j sqrt(dt / V+_j) / 2 */
+                       then (Milstein) the path's largest d sqrt(V+ dt) / dV+ =
+                       max_j sqrt(dt / V+_j) / 2, or (QE) its smallest branch margin */
 
 typedef struct {
     double S0, K, r, T, v0, kappa, theta, sigma, rho;
@@ -469,6 +471,154 @@ static void tan_path(const or_params *P, int type, uint32_t N, const uint8_t *fi
     out[1 + NP] = amp;
 }
 
+/* Forward-mode derivatives of one QE path's discounted payoff with respect to
+ * (S0, v0, r, kappa, theta, sigma, rho): Andersen's step (qe_variance, the
+ * log-price update of sim_path_qe) differentiated by the chain rule through
+ * E = e^{-kappa dt}, the conditional moments m and s2, psi = s2 / m^2 and the
+ * branch the step takes; the branch decisions themselves (psi against psi_c,
+ * Uv against p) are held fixed, and the point mass at zero has derivative 0.
+ * The derivative of sqrt(K3 V + K4 V') is taken as 0 where its argument is 0.
+ * out[0..7] as tan_path; out[8] = the path's smallest branch margin (as
+ * sim_path_qe reports it), below which a bump can switch a branch.          */
+static void tan_path_qe(const or_params *P, int type, uint32_t N, const uint8_t *fix,
+                        uint32_t n_fix, uint64_t seed, uint64_t path, double *out)
+{
+    enum { I_S0 = 0, I_V0, I_R, I_KAPPA, I_THETA, I_SIGMA, I_RHO };
+    const double dt = P->T / (double)N;
+    const double kap = P->kappa, th = P->theta, sig = P->sigma, rho = P->rho;
+    const double g1 = 0.5, g2 = 0.5;
+    /* log-price coefficients (as sim_path_qe) and their partials */
+    const double c = kap * rho / sig - 0.5;
+    const double K0 = -rho * kap * th * dt / sig;
+    const double K1 = g1 * dt * c - rho / sig;
+    const double K2 = g2 * dt * c + rho / sig;
+    const double K3 = g1 * dt * (1.0 - rho * rho);
+    const double K4 = g2 * dt * (1.0 - rho * rho);
+    double dK0[NP] = { 0 }, dK1[NP] = { 0 }, dK2[NP] = { 0 }, dK34[NP] = { 0 };
+    dK0[I_KAPPA] = -rho * th * dt / sig;
+    dK0[I_THETA] = -rho * kap * dt / sig;
+    dK0[I_SIGMA] = rho * kap * th * dt / (sig * sig);
+    dK0[I_RHO] = -kap * th * dt / sig;
+    const double dc_dk = rho / sig, dc_ds = -kap * rho / (sig * sig), dc_dr = kap / sig;
+    dK1[I_KAPPA] = g1 * dt * dc_dk;
+    dK1[I_SIGMA] = g1 * dt * dc_ds + rho / (sig * sig);
+    dK1[I_RHO] = g1 * dt * dc_dr - 1.0 / sig;
+    dK2[I_KAPPA] = g2 * dt * dc_dk;
+    dK2[I_SIGMA] = g2 * dt * dc_ds - rho / (sig * sig);
+    dK2[I_RHO] = g2 * dt * dc_dr + 1.0 / sig;
+    dK34[I_RHO] = -2.0 * g1 * dt * rho; /* K3 = K4 */
+    /* variance-step constants: m = theta + (V - theta) E,
+     * s2 = sigma^2 (V A1 + theta A0), A1 = E (1-E) / kappa, A0 = (1-E)^2 / (2 kappa) */
+    const double E = exp(-kap * dt), dE = -dt * E; /* dE / dkappa */
+    const double s2s = sig * sig;
+    const double A1 = E * (1.0 - E) / kap, A0 = (1.0 - E) * (1.0 - E) / (2.0 * kap);
+    const double dA1 = dE * (1.0 - 2.0 * E) / kap - A1 / kap;
+    const double dA0 = -(1.0 - E) * dE / kap - A0 / kap;
+
+    double S = P->S0, dS[NP] = { 0 };
+    double V = P->v0, dV[NP] = { 0 };
+    double A = 0.0, dA[NP] = { 0 };
+    double margin = INFINITY;
+    dS[I_S0] = 1.0;
+    dV[I_V0] = 1.0;
+    for (uint32_t j = 0; j < N; ++j) {
+        double zs, zv, uv, mg;
+        or_qe_draws(seed, path, j, &zs, &zv, &uv);
+        const double Vn = qe_variance(P, dt, V, zv, uv, &mg);
+        if (mg < margin)
+            margin = mg;
+        /* the moments and psi, with derivatives */
+        const double m = th + (V - th) * E;
+        const double s2 = s2s * (V * A1 + th * A0);
+        const double psi = s2 / (m * m);
+        double dm[NP], ds2[NP], dpsi[NP], dVn[NP];
+        for (int k = 0; k < NP; ++k) {
+            dm[k] = E * dV[k];
+            ds2[k] = s2s * A1 * dV[k];
+        }
+        dm[I_KAPPA] += (V - th) * dE;
+        dm[I_THETA] += 1.0 - E;
+        ds2[I_KAPPA] += s2s * (V * dA1 + th * dA0);
+        ds2[I_THETA] += s2s * A0;
+        ds2[I_SIGMA] += 2.0 * sig * (V * A1 + th * A0);
+        for (int k = 0; k < NP; ++k)
+            dpsi[k] = ds2[k] / (m * m) - 2.0 * s2 * dm[k] / (m * m * m);
+        if (psi <= OR_QE_PSI_C) {
+            /* Vn = a (b + Zv)^2, b^2 = 2/psi - 1 + sqrt(2/psi) sqrt(2/psi - 1), a = m / (1 + b^2) */
+            const double inv = 2.0 / psi;
+            const double r = sqrt(inv) * sqrt(inv - 1.0);
+            const double b2 = inv - 1.0 + r;
+            const double a = m / (1.0 + b2);
+            const double b = sqrt(b2);
+            const double db2_dinv = 1.0 + (2.0 * inv - 1.0) / (2.0 * r);
+            for (int k = 0; k < NP; ++k) {
+                const double dinv = -2.0 * dpsi[k] / (psi * psi);
+                const double db2 = db2_dinv * dinv;
+                const double da = dm[k] / (1.0 + b2) - m * db2 / ((1.0 + b2) * (1.0 + b2));
+                const double db = db2 / (2.0 * b);
+                dVn[k] = da * (b + zv) * (b + zv) + 2.0 * a * (b + zv) * db;
+            }
+        } else {
+            /* point mass at 0 with probability p, else Vn = m / (1-p) ln((1-p) / (1-Uv)) */
+            const double p = (psi - 1.0) / (psi + 1.0);
+            if (uv <= p) {
+                for (int k = 0; k < NP; ++k)
+                    dVn[k] = 0.0;
+            } else {
+                const double L = log((1.0 - p) / (1.0 - uv));
+                for (int k = 0; k < NP; ++k) {
+                    const double dp = 2.0 * dpsi[k] / ((psi + 1.0) * (psi + 1.0));
+                    dVn[k] = dm[k] * L / (1.0 - p) + m * (L - 1.0) * dp / ((1.0 - p) * (1.0 - p));
+                }
+            }
+        }
+        /* log-price step */
+        const double q = K3 * V + K4 * Vn;
+        const double sq = sqrt(q);
+        const double inc = P->r * dt + K0 + K1 * V + K2 * Vn + sq * zs;
+        double dinc[NP];
+        for (int k = 0; k < NP; ++k) {
+            const double dq = K3 * dV[k] + K4 * dVn[k] + dK34[k] * (V + Vn);
+            const double dsq = q > 0.0 ? dq / (2.0 * sq) : 0.0;
+            dinc[k] = dK0[k] + dK1[k] * V + K1 * dV[k] + dK2[k] * Vn + K2 * dVn[k] + dsq * zs;
+        }
+        dinc[I_R] += dt;
+        const double g = exp(inc);
+        const double Snew = S * g;
+        for (int k = 0; k < NP; ++k)
+            dS[k] = g * dS[k] + Snew * dinc[k];
+        S = Snew;
+        V = Vn;
+        for (int k = 0; k < NP; ++k)
+            dV[k] = dVn[k];
+        if (fix[j + 1]) {
+            A += S;
+            for (int k = 0; k < NP; ++k)
+                dA[k] += dS[k];
+        }
+    }
+    const double D = exp(-P->r * P->T);
+    double X, dX[NP];
+    if (is_asian(type)) {
+        X = A / (double)n_fix;
+        for (int k = 0; k < NP; ++k)
+            dX[k] = dA[k] / (double)n_fix;
+    } else {
+        X = S;
+        for (int k = 0; k < NP; ++k)
+            dX[k] = dS[k];
+    }
+    const double sgn = is_call(type) ? 1.0 : -1.0;
+    const double intrinsic = sgn * (X - P->K);
+    const int itm = intrinsic > 0.0;
+    const double pay = D * (itm ? intrinsic : 0.0);
+    out[0] = pay;
+    for (int k = 0; k < NP; ++k)
+        out[1 + k] = itm ? D * sgn * dX[k] : 0.0;
+    out[1 + I_R] += -P->T * pay;
+    out[1 + NP] = margin;
+}
+
 /* ------------------------------------------------------------------------ */
 typedef struct {
     const or_params *P;
@@ -485,7 +635,10 @@ static void *run_job(void *arg)
     or_job *jb = (or_job *)arg;
     for (uint64_t row = jb->lo; row < jb->hi; ++row) {
         uint64_t path = jb->first + row;
-        if (jb->tangent)
+        if (jb->tangent && jb->mode == OR_QE)
+            tan_path_qe(jb->P, jb->type, jb->N, jb->fix, jb->n_fix, jb->src->seed, path,
+                        jb->out + row * OR_TAN);
+        else if (jb->tangent)
             tan_path(jb->P, jb->type, jb->N, jb->fix, jb->n_fix, jb->mode, jb->src, path, row,
                      jb->out + row * OR_TAN);
         else if (jb->mode == OR_QE)
@@ -510,11 +663,11 @@ static int run(const or_params *P, int type, uint32_t N, const uint32_t *fix_ste
         return -1;
     if (tangent && is_geo(type))
         return -1; /* the tangent path covers the European and arithmetic payoffs */
-    if (tangent && mode != OR_FULL_TRUNC && mode != OR_ABSORB)
-        return -1; /* the tangent path follows the Milstein scheme */
-    /* QE draws its own Philox inputs (no caller normals), needs sigma > 0 and
-     * theta > 0, and has no tangent path. */
-    if (mode == OR_QE && (za || zb || tangent || !(P->sigma > 0.0) || !(P->theta > 0.0)))
+    if (tangent && mode != OR_FULL_TRUNC && mode != OR_ABSORB && mode != OR_QE)
+        return -1; /* the tangent paths follow the Milstein and QE schemes */
+    /* QE draws its own Philox inputs (no caller normals) and needs sigma > 0
+     * and theta > 0. */
+    if (mode == OR_QE && (za || zb || !(P->sigma > 0.0) || !(P->theta > 0.0)))
         return -1;
     uint8_t *fix = (uint8_t *)calloc((size_t)N + 1, 1);
     if (!fix)
