@@ -380,7 +380,7 @@ typedef struct heston_request {
  * fixing_steps must be NULL.  Blocks until done; device_ms (nullable) gets the
  * GPU time of the batched kernels.  Errors: INVALID_ARGUMENT (any request
  * invalid; nothing is priced), UNSUPPORTED, OVER_BUDGET / OUT_OF_MEMORY
- * (item records: 128 bytes per 1024 paths), DEVICE_ERROR. */
+ * (item records: 512 bytes per 1024 paths), DEVICE_ERROR. */
 heston_status heston_price_batch(heston_ctx *ctx, const heston_request *reqs, uint32_t n,
                                  const heston_opts *opts, heston_result *out, double *device_ms);
 
@@ -390,7 +390,7 @@ heston_status heston_price_batch(heston_ctx *ctx, const heston_request *reqs, ui
  * A server owns an engine thread and device memory on the context's device.
  * heston_submit enqueues a request and returns at once with a ticket.  The
  * engine admits queued requests while the server's device-memory budget and
- * request slots allow (a request holds 128 bytes per 1024-path item of its path
+ * request slots allow (a request holds 512 bytes per 1024-path item of its path
  * cap plus a 256-byte state), and repeatedly launches the batched kernel over
  * the next items of every admitted request, so requests that arrive while
  * others run join the next launch and their work overlaps on the device.

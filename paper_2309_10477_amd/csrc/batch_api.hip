@@ -97,13 +97,13 @@ heston_status run_batch(heston_ctx *c, BatchWork &w, int precision, int scheme, 
         (st = reserve(c, c->batch_items, std::max<size_t>(n_items, 1) * 4)) != HESTON_OK ||
         (st = reserve(c, c->batch_counter, 16)) != HESTON_OK)
         return st;
-    // item records: the option's own slot array when given, else one shared array
+    // unit records: the option's own slot array when given, else one shared array
     if (w.partials == nullptr) {
-        if ((st = reserve(c, c->batch_partials, std::max<size_t>(n_items, 1) * N_ACC * 8)) !=
+        if ((st = reserve(c, c->batch_partials, std::max<size_t>(n_items, 1) * ITEM_REC * 8)) !=
             HESTON_OK)
             return st;
         for (auto &o : w.opts)
-            o.partials = (double *)c->batch_partials.ptr + (uint64_t)o.first_item * N_ACC;
+            o.partials = (double *)c->batch_partials.ptr + (uint64_t)o.first_item * ITEM_REC;
     }
     int grid_price = 0, grid_adj = 0;
     if (w.n_price_items)
@@ -135,7 +135,7 @@ heston_status run_batch(heston_ctx *c, BatchWork &w, int precision, int scheme, 
         B.item_begin = 0;
         B.item_end = w.n_price_items;
         B.counter = (uint32_t *)c->batch_counter.ptr;
-        B.grid = (uint32_t)std::min<uint64_t>(grid_price, w.n_price_items);
+        B.grid = (uint32_t)std::min<uint64_t>(grid_price, (uint64_t)w.n_price_items * BATCH_UNITS);
         HIP_TRY(launch_batch(B, c->stream));
     }
     if (n_items > w.n_price_items) {
@@ -145,7 +145,8 @@ heston_status run_batch(heston_ctx *c, BatchWork &w, int precision, int scheme, 
         B.counter = (uint32_t *)c->batch_counter.ptr + 1;
         B.scratch = (unsigned char *)c->batch_scratch.ptr;
         B.scratch_per_block = per_block;
-        B.grid = (uint32_t)std::min<uint64_t>(grid_adj, n_items - w.n_price_items);
+        B.grid = (uint32_t)std::min<uint64_t>(grid_adj,
+                                              (uint64_t)(n_items - w.n_price_items) * BATCH_UNITS);
         HIP_TRY(launch_batch(B, c->stream));
     }
     HIP_TRY(hipEventRecord(c->ev1, c->stream));

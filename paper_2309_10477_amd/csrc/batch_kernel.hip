@@ -2,14 +2,15 @@
 //
 // The work is a list of items; item g is chunk chunk_base[o] + (g - first_item[o])
 // of option o = item_opt[g], i.e. paths [chunk * CHUNK, (chunk + 1) * CHUNK) of
-// that option's own stream.  A grid sized to the resident capacity of the chip
-// pops item indices from one device counter until the list is exhausted, so
-// every workgroup ends when the counter passes the last item.  Items are
-// ordered by decreasing cost (longest step counts first), so the tail of the
-// launch holds the cheapest items.  Each item writes one FP64 partial record;
-// a second kernel sums every option's records in item order.  The partial of
-// an item depends only on its own paths and the option's sum only on the
-// item order, so an option's result is bitwise the same alone or in any batch.
+// that option's own stream, run as BATCH_UNITS units of BLOCK paths.  A grid
+// sized to the resident capacity of the chip pops unit indices from one device
+// counter until the list is exhausted, so every workgroup ends when the
+// counter passes the last unit.  Items are ordered by decreasing cost (longest
+// step counts first), so the tail of the launch holds the cheapest units.
+// Each unit writes one FP64 partial record; a second kernel sums every
+// option's records in unit order.  The partial of a unit depends only on its
+// own paths and the option's sum only on the unit order, so an option's result
+// is bitwise the same alone or in any batch.
 //
 // Per item and path: the Milstein path of the paper's algorithm "Milstein
 // approximation under Heston model" in R, payoff and pathwise estimators in
@@ -22,41 +23,38 @@
 namespace heston {
 namespace {
 
-// Runs the item's BATCH_CHUNK paths, 256 at a time; after each sub-block the
-// wave's sums are added to its LDS row red[wave] (FP64, sub-block order).
+// Runs unit `sub` of an item (its paths sub BLOCK .. sub BLOCK + BLOCK-1);
+// the wave sums go to the LDS row red[wave].
 template <class R, bool ASIAN, bool FT, bool ADJ>
-__device__ __forceinline__ void run_item_paths(const BatchOption &op, uint64_t chunk, R *scratch,
-                                               double (*red)[N_ACC])
+__device__ __forceinline__ void run_unit_paths(const BatchOption &op, uint64_t chunk, uint32_t sub,
+                                               R *scratch, double (*red)[N_ACC])
 {
     const uint32_t tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll 1
-    for (uint32_t sub = 0; sub < BATCH_CHUNK / BLOCK; ++sub) {
-        const uint64_t p = chunk * BATCH_CHUNK + (uint64_t)sub * BLOCK + tid;
-        const bool active = p < op.n_paths;
-        double out[8];
-        if constexpr (ADJ) {
-            R x, v, A, B;
-            forward_path<R, ASIAN, FT>(op.k, p, x, v, A, B, scratch, BLOCK, tid, BATCH_CKPT_EVERY);
-            __threadfence_block();
-            adjoint_path<R, ASIAN, FT, BATCH_CKPT_EVERY>(op.k, p, scratch, BLOCK, tid, out);
-        } else {
-            R x, v, A, B;
-            forward_path<R, ASIAN, FT>(op.k, p, x, v, A, B, nullptr, 0, 0, 2);
-            path_estimators<ASIAN>(op.k, (double)x, (double)A, (double)B, out[0], out[1], out[2]);
+    const uint64_t p = chunk * BATCH_CHUNK + (uint64_t)sub * BLOCK + tid;
+    const bool active = p < op.n_paths;
+    double out[8];
+    if constexpr (ADJ) {
+        R x, v, A, B;
+        forward_path<R, ASIAN, FT>(op.k, p, x, v, A, B, scratch, BLOCK, tid, BATCH_CKPT_EVERY);
+        __threadfence_block();
+        adjoint_path<R, ASIAN, FT, BATCH_CKPT_EVERY>(op.k, p, scratch, BLOCK, tid, out);
+    } else {
+        R x, v, A, B;
+        forward_path<R, ASIAN, FT>(op.k, p, x, v, A, B, nullptr, 0, 0, 2);
+        path_estimators<ASIAN>(op.k, (double)x, (double)A, (double)B, out[0], out[1], out[2]);
 #pragma unroll
-            for (int e = 3; e < 8; ++e)
-                out[e] = 0.0;
-        }
+        for (int e = 3; e < 8; ++e)
+            out[e] = 0.0;
+    }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const double y = active ? out[e] : 0.0;
-            const double s1 = wave_sum(y);
-            const double s2 = wave_sum(y * y);
-            if (lane == 0) {
-                red[wave][2 * e] += s1;
-                red[wave][2 * e + 1] += s2;
-            }
+    for (int e = 0; e < 8; ++e) {
+        const double y = active ? out[e] : 0.0;
+        const double s1 = wave_sum(y);
+        const double s2 = wave_sum(y * y);
+        if (lane == 0) {
+            red[wave][2 * e] = s1;
+            red[wave][2 * e + 1] = s2;
         }
     }
 }
@@ -79,42 +77,40 @@ void batch_kernel(const BatchOption *__restrict__ opts,
                                                       unsigned char *scratch,
                                                       uint64_t scratch_per_block)
 {
-    __shared__ uint32_t s_item;
+    __shared__ uint32_t s_unit;
     __shared__ double red[BLOCK / 64][N_ACC];
     R *my_scratch = reinterpret_cast<R *>(scratch + (uint64_t)blockIdx.x * scratch_per_block);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t n_units = (item_end - item_begin) * BATCH_UNITS;
     for (;;) {
         if (threadIdx.x == 0)
-            s_item = atomicAdd(counter, 1u);
+            s_unit = atomicAdd(counter, 1u);
         __syncthreads();
-        const uint32_t pos = __builtin_amdgcn_readfirstlane(s_item);
+        const uint32_t pos = __builtin_amdgcn_readfirstlane(s_unit);
         __syncthreads();
-        if (pos >= item_end - item_begin)
+        if (pos >= n_units)
             break;
-        const uint32_t g = item_begin + pos;
+        const uint32_t g = item_begin + pos / BATCH_UNITS, sub = pos % BATCH_UNITS;
         const uint32_t o = __builtin_amdgcn_readfirstlane(item_opt[g]);
         const BatchOption &op = opts[o];
         const uint32_t i = g - op.first_item;
         const uint64_t chunk = op.chunk_base + i;
-        if (lane < N_ACC)
-            red[wave][lane] = 0.0;
         if (op.k.type >= 2)
-            run_item_paths<R, true, FT, ADJ>(op, chunk, my_scratch, red);
+            run_unit_paths<R, true, FT, ADJ>(op, chunk, sub, my_scratch, red);
         else
-            run_item_paths<R, false, FT, ADJ>(op, chunk, my_scratch, red);
+            run_unit_paths<R, false, FT, ADJ>(op, chunk, sub, my_scratch, red);
         __syncthreads();
         if (threadIdx.x < N_ACC) {
             double t = 0.0;
 #pragma unroll
             for (int w = 0; w < BLOCK / 64; ++w)
                 t += red[w][threadIdx.x];
-            op.partials[(uint64_t)i * N_ACC + threadIdx.x] = t;
+            op.partials[((uint64_t)i * BATCH_UNITS + sub) * N_ACC + threadIdx.x] = t;
         }
     }
 }
 
-// Option o's sums: its items' partial records added in item order.  Thread t
-// owns column t % N_ACC and items i = t / N_ACC (mod BLOCK / N_ACC); the
+// Option o's sums: its unit records added in unit order.  Thread t owns
+// column t % N_ACC and units u = t / N_ACC (mod BLOCK / N_ACC); the
 // BLOCK / N_ACC per-column partials are then added in a fixed order.
 __global__ __launch_bounds__(BLOCK) void batch_reduce_kernel(const BatchOption *__restrict__ opts,
                                                              double *__restrict__ sums)
@@ -123,9 +119,10 @@ __global__ __launch_bounds__(BLOCK) void batch_reduce_kernel(const BatchOption *
     __shared__ double red[LANES][N_ACC];
     const BatchOption &op = opts[blockIdx.x];
     const int col = threadIdx.x % N_ACC, slot = threadIdx.x / N_ACC;
+    const uint64_t n_units = (uint64_t)op.n_items * BATCH_UNITS;
     double t = 0.0;
-    for (uint32_t i = slot; i < op.n_items; i += LANES)
-        t += op.partials[(uint64_t)i * N_ACC + col];
+    for (uint64_t u = slot; u < n_units; u += LANES)
+        t += op.partials[u * N_ACC + col];
     red[slot][col] = t;
     __syncthreads();
     if (threadIdx.x < N_ACC) {

@@ -160,12 +160,17 @@ struct PathConsts {
 
 // Batched launches: one option (request) of a batch and the launch itself.
 constexpr uint32_t BATCH_CHUNK = 1024;     // paths per work item (4 x BLOCK)
+// An item runs as BATCH_UNITS units of BLOCK paths, each a unit of dynamic
+// scheduling with its own partial record; an item's record is the sum of its
+// units' records in unit order (ITEM_REC doubles per item).
+constexpr uint32_t BATCH_UNITS = BATCH_CHUNK / BLOCK;
+constexpr int ITEM_REC = (int)BATCH_UNITS * N_ACC;
 constexpr int BATCH_CKPT_EVERY = 8;        // adjoint checkpoint interval in batches
 struct BatchOption {
     PathConsts k;
     uint64_t n_paths;
     uint64_t chunk_base;      // chunk index of the option's first item in this launch
-    double *partials;         // device: record of item first_item + i at partials + i N_ACC
+    double *partials;         // device: unit u of item first_item + i at partials + (i BATCH_UNITS + u) N_ACC
     uint32_t first_item, n_items;
     uint32_t adjoint; // 0: price + pathwise Delta/Rho; 1: price + 7 adjoint sensitivities
     uint32_t pad;
@@ -184,7 +189,7 @@ struct BatchLaunch {
 };
 int batch_resident_blocks(int precision, int scheme, bool adjoint);
 hipError_t launch_batch(const BatchLaunch &B, hipStream_t s);
-// sums[o][N_ACC]: option o's n_items records (at opts[o].partials) added in order.
+// sums[o][N_ACC]: option o's unit records (at opts[o].partials) added in order.
 hipError_t launch_batch_reduce(const BatchLaunch &B, double *sums, hipStream_t s);
 
 // Checkpoint buffer of the adjoint, structure of arrays in the path state's

@@ -3,7 +3,8 @@
 // Engine thread:
 //   1. admit queued requests while request slots and the device-memory budget
 //      allow; a request's device state is a 256-byte record of running sums
-//      plus one 128-byte record per 1024-path item of its path cap;
+//      plus one 512-byte record per 1024-path item of its path cap (one
+//      128-byte record per 256-path unit);
 //   2. launch: take the next items of every schedulable admitted request
 //      (a fair share of the per-launch work each), run the batched kernel over
 //      them, then the fold kernel, which extends every request's running sums
@@ -12,8 +13,9 @@
 //      the stream, so new requests join while earlier ones run;
 //   3. complete: when a launch's event has fired, requests whose state says
 //      done get their result and latency recorded, and their memory is freed.
-// A request with an SE target is scheduled one launch at a time: after each
-// fold the engine asks for as many further items as the observed SE implies.
+// A request with an SE target is scheduled up to the items its observed SE
+// implies (16 before its first fold), in as many pipelined launches as its
+// fair share spreads them over; each fold refines the estimate.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,9 +65,21 @@ struct FoldTask {
     double se_target;
 };
 
+// Column k of item i's record: the sum of its unit records in unit order.
+__device__ __forceinline__ double item_col(const double *records, uint32_t i, uint32_t k)
+{
+    const double *r = records + (uint64_t)i * ITEM_REC + k;
+    double t = r[0];
+#pragma unroll
+    for (uint32_t u = 1; u < BATCH_UNITS; ++u)
+        t += r[u * N_ACC];
+    return t;
+}
+
 // One block per task: thread 0 walks the new items (price sums only) to find
 // where the stopping rule fires; then thread k < N_ACC adds column k of those
-// items in order.
+// items in order.  An item's record is its BATCH_UNITS unit records added in
+// unit order.
 __global__ __launch_bounds__(64) void fold_kernel(const FoldTask *__restrict__ tasks,
                                                   ReqState *__restrict__ out)
 {
@@ -91,8 +105,8 @@ __global__ __launch_bounds__(64) void fold_kernel(const FoldTask *__restrict__ t
         if (!done) {
             double s = st->sums[0], ss = st->sums[1];
             for (uint32_t i = st->folded; i < t.upto; ++i) {
-                s += t.records[(uint64_t)i * N_ACC + 0];
-                ss += t.records[(uint64_t)i * N_ACC + 1];
+                s += item_col(t.records, i, 0);
+                ss += item_col(t.records, i, 1);
                 const uint64_t paths = std::min<uint64_t>((uint64_t)(i + 1) * BATCH_CHUNK,
                                                           st->cap_paths);
                 const double n = (double)paths, m = s / n;
@@ -115,7 +129,7 @@ __global__ __launch_bounds__(64) void fold_kernel(const FoldTask *__restrict__ t
     if (threadIdx.x < N_ACC && !st->done) {
         double acc = st->sums[threadIdx.x];
         for (uint32_t i = st->folded; i < stop; ++i)
-            acc += t.records[(uint64_t)i * N_ACC + threadIdx.x];
+            acc += item_col(t.records, i, threadIdx.x);
         st->sums[threadIdx.x] = acc;
     }
     __syncthreads();
@@ -260,17 +274,19 @@ void admit(heston_server *s)
 {
     s->stats.admitted += admit_in_order(
         s->queue, s->active, s->cfg.max_active, s->pool,
-        [](const Req *q) { return sizeof(ReqState) + (uint64_t)q->cap_items * N_ACC * 8; },
+        [](const Req *q) { return sizeof(ReqState) + (uint64_t)q->cap_items * ITEM_REC * 8; },
         [](Req *q, unsigned char *m) { q->mem = m; });
 }
 
-// Items a request asks for in the next launch.
+// Items a request asks for in the next launch.  A request with an SE target
+// asks for items up to its current estimate of the items it needs, also while
+// earlier launches of it are in flight (launches are pipelined); the fold
+// stops at the first item that meets the target, so items beyond it are
+// computed and ignored, and the result does not depend on the scheduling.
 uint32_t wanted_items(const Req *q)
 {
     if (q->done || q->scheduled >= q->cap_items)
         return 0;
-    if (q->r.se_target > 0 && q->inflight > 0)
-        return 0; // wait for the fold to decide
     const uint32_t goal = q->r.se_target > 0 ? std::min(q->target, q->cap_items) : q->cap_items;
     return goal > q->scheduled ? goal - q->scheduled : 0;
 }
@@ -319,7 +335,7 @@ heston_status launch_next(heston_server *s, bool &launched)
     for (size_t j = 0; j < w.opts.size(); ++j) {
         Req *q = sel[w.order[j]];
         heston::BatchOption &o = w.opts[j];
-        o.partials = q->records() + (uint64_t)o.chunk_base * N_ACC;
+        o.partials = q->records() + (uint64_t)o.chunk_base * ITEM_REC;
         L.h_opts[j] = o;
         L.h_tasks[j] = FoldTask{q->state(), q->records(), (uint32_t)(o.chunk_base + o.n_items),
                                 (uint32_t)j, q->started ? 0u : 1u, q->cap_items, q->r.n_paths,
@@ -349,7 +365,7 @@ heston_status launch_next(heston_server *s, bool &launched)
         B.item_begin = 0;
         B.item_end = w.n_price_items;
         B.counter = (uint32_t *)L.counter.ptr;
-        B.grid = std::min<uint32_t>(s->grid_price, w.n_price_items);
+        B.grid = std::min<uint32_t>(s->grid_price, w.n_price_items * BATCH_UNITS);
         HIP_TRY(launch_batch(B, sm));
     }
     if (n_items > w.n_price_items) {
@@ -359,7 +375,7 @@ heston_status launch_next(heston_server *s, bool &launched)
         B.counter = (uint32_t *)L.counter.ptr + 1;
         B.scratch = (unsigned char *)s->scratch.ptr;
         B.scratch_per_block = s->scratch_per_block;
-        B.grid = std::min<uint32_t>(s->grid_adj, n_items - w.n_price_items);
+        B.grid = std::min<uint32_t>(s->grid_adj, (n_items - w.n_price_items) * BATCH_UNITS);
         HIP_TRY(launch_batch(B, sm));
     }
     hipLaunchKernelGGL(fold_kernel, dim3(n_opts), dim3(64), 0, sm, (const FoldTask *)L.tasks.ptr,
@@ -625,7 +641,7 @@ heston_status heston_submit(heston_server *s, const heston_request *req, uint64_
     if (req->n_steps > s->cfg.max_steps)
         return fail(HESTON_INVALID_ARGUMENT, "n_steps above the server's max_steps");
     const uint64_t items = (req->n_paths + BATCH_CHUNK - 1) / BATCH_CHUNK;
-    if (items >= (1ull << 31) || sizeof(ReqState) + items * N_ACC * 8 > s->pool_buf.bytes)
+    if (items >= (1ull << 28) || sizeof(ReqState) + items * ITEM_REC * 8 > s->pool_buf.bytes)
         return fail(HESTON_INVALID_ARGUMENT, "path cap too large for the server's budget");
     Req *r = new Req;
     r->r = *req;

@@ -141,7 +141,7 @@ def test_tiny_budget_queues_but_completes(hm, ctx):
     srv = hm.Server(ctx, precision=hm.FP32, max_steps=128, hbm_budget_bytes=1 << 30)
     pool = srv.stats()["pool_bytes"]
     srv.close()
-    per_req = 256 + 128 * max(math.ceil(q["n_paths"] / 1024) for q in reqs)
+    per_req = 256 + 512 * max(math.ceil(q["n_paths"] / 1024) for q in reqs)
     budget = (1 << 30) - pool + 3 * per_req + 4096
     srv = hm.Server(ctx, precision=hm.FP32, max_steps=128, hbm_budget_bytes=budget)
     try:
