@@ -98,6 +98,9 @@ def lib():
         L.or_uniform.restype = ctypes.c_double
         L.or_qe_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, dp, dp, dp]
         L.or_qe_draws.restype = None
+        L.or_qe_draws_block.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.c_uint32, dp, dp, dp]
+        L.or_qe_draws_block.restype = None
         _lib = L
     return _lib
 
@@ -162,6 +165,14 @@ def qe_draws(seed: int, path: int, step: int):
     lib().or_qe_draws(seed & (2**64 - 1), path, step, ctypes.byref(zs), ctypes.byref(zv),
                       ctypes.byref(uv))
     return zs.value, zv.value, uv.value
+
+
+def qe_draws_block(seed: int, first: int, n_paths: int, n_steps: int):
+    """The QE scheme's random inputs (Zs, Zv, Uv), each [n_paths, n_steps]."""
+    zs, zv, uv = (np.empty((n_paths, n_steps)) for _ in range(3))
+    lib().or_qe_draws_block(seed & (2**64 - 1), first, n_paths, n_steps, _ptr(zs, ctypes.c_double),
+                            _ptr(zv, ctypes.c_double), _ptr(uv, ctypes.c_double))
+    return zs, zv, uv
 
 
 def tangent(p: Params, opt_type: int, n_steps: int, seed: int = 0, first: int = 0,

@@ -745,6 +745,15 @@ void or_normals_block(uint64_t seed, uint64_t first, uint64_t n_paths, uint32_t 
             or_normals(seed, first + p, j, &za[p * N + j], &zb[p * N + j]);
 }
 
+/* Bulk QE inputs for tests: zs/zv/uv [n_paths][N] for paths first.. */
+void or_qe_draws_block(uint64_t seed, uint64_t first, uint64_t n_paths, uint32_t N, double *zs,
+                       double *zv, double *uv)
+{
+    for (uint64_t p = 0; p < n_paths; ++p)
+        for (uint32_t j = 0; j < N; ++j)
+            or_qe_draws(seed, first + p, j, &zs[p * N + j], &zv[p * N + j], &uv[p * N + j]);
+}
+
 void or_philox_block(const uint32_t *ctr, const uint32_t *key, uint64_t n, uint32_t *out)
 {
     for (uint64_t i = 0; i < n; ++i)

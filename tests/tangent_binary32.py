@@ -1,5 +1,5 @@
-"""The Milstein path and its forward-mode derivatives evaluated in binary32 on
-the CPU -- test infrastructure.
+"""The Milstein or QE path and its forward-mode derivatives evaluated in
+binary32 on the CPU -- test infrastructure.
 
 The single-precision adjoint kernels carry a path's state (log-price,
 variance, running average) and, in the reverse sweep, its adjoints in
@@ -32,8 +32,15 @@ the GPU path.  With binary64 and no perturbation it reproduces the oracle's
 derivatives to 1e-13 on well-conditioned paths (a CPU test checks this),
 which pins its formulas.
 
+Under Andersen's QE scheme the same holds where the quadratic branch's
+b + Zv nearly cancels (V' = a (b + Zv)^2 then carries the relative error of
+Zv divided by |b + Zv|) and where a step sits close to the branch switch
+psi = 3/2 or to the point mass of the exponential branch; there the inputs are
+(Zs, Zv, Uv), the oracle's QE draws, and the branch decisions are taken on the
+evaluation's own rounded values.
+
 Columns: 0 payoff, 1..7 d/d(S0, v0, r, kappa, theta, sigma, rho), 8 the
-path's largest d sqrt(V+ dt)/dV+ (as the oracle reports it).
+Milstein path's largest d sqrt(V+ dt)/dV+ (as the oracle reports it); 0 for QE.
 """
 from __future__ import annotations
 
@@ -80,26 +87,32 @@ def lib():
         P = ctypes.POINTER
         L.tm_evaluate.argtypes = [P(_CParams), ctypes.c_int, ctypes.c_uint32, P(ctypes.c_uint8),
                                   ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double),
-                                  ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
-                                  P(ctypes.c_double)]
+                                  P(ctypes.c_double), ctypes.c_uint64, ctypes.c_int,
+                                  ctypes.c_uint64, ctypes.c_int, P(ctypes.c_double)]
         L.tm_evaluate.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def inputs(p, opt_type, n_steps, seed, first, n, mode=oracle.FULL_TRUNC):
+    """The random inputs both sides consume: (Za, Zb) for Milstein, (Zs, Zv, Uv) for QE."""
+    if mode == oracle.QE:
+        return oracle.qe_draws_block(seed, first, n, n_steps)
+    return oracle.normals(seed, first, n, n_steps)
 
 
 def evaluate(p, opt_type, n_steps, seed, first, n, mode=oracle.FULL_TRUNC, fixings=None,
              dtype=np.float32, mca_seed=0, normals=None, threads=8):
     """One evaluation in ``dtype`` (round to nearest for ``mca_seed`` 0, else
     Monte Carlo arithmetic from that seed); [n, 9] in the oracle's tangent
-    layout."""
-    if mode not in (oracle.FULL_TRUNC, oracle.ABSORB):
-        raise ValueError("the derivative path follows the Milstein scheme")
+    layout (column 8: the Milstein path's largest sqrt(dt / V+) / 2; 0 for QE)."""
+    if mode not in (oracle.FULL_TRUNC, oracle.ABSORB, oracle.QE):
+        raise ValueError("the derivative path follows the Milstein or QE scheme")
     if opt_type not in (0, 1, 2, 3):
         raise ValueError("European and arithmetic-average Asian payoffs only")
-    za, zb = normals if normals is not None else oracle.normals(seed, first, n, n_steps)
-    za = np.ascontiguousarray(za, np.float64)
-    zb = np.ascontiguousarray(zb, np.float64)
-    assert za.shape == (n, n_steps) and zb.shape == za.shape
+    z = normals if normals is not None else inputs(p, opt_type, n_steps, seed, first, n, mode)
+    z = [np.ascontiguousarray(a, np.float64) for a in z]
+    assert all(a.shape == (n, n_steps) for a in z) and len(z) == (3 if mode == oracle.QE else 2)
     fix = np.zeros(n_steps + 1, np.uint8)
     if fixings is None:
         fix[1:] = 1
@@ -107,13 +120,14 @@ def evaluate(p, opt_type, n_steps, seed, first, n, mode=oracle.FULL_TRUNC, fixin
         fix[np.asarray(fixings)] = 1
     out = np.empty((n, 9))
     P = ctypes.POINTER
+    dp = P(ctypes.c_double)
     cp = _CParams(p.S0, p.K, p.r, p.T, p.v0, p.kappa, p.theta, p.sigma, p.rho)
+    scheme = {oracle.FULL_TRUNC: 0, oracle.ABSORB: 1, oracle.QE: 2}[mode]
     rc = lib().tm_evaluate(ctypes.byref(cp), opt_type, n_steps,
-                           fix.ctypes.data_as(P(ctypes.c_uint8)), int(mode == oracle.ABSORB),
-                           za.ctypes.data_as(P(ctypes.c_double)),
-                           zb.ctypes.data_as(P(ctypes.c_double)), n,
-                           int(dtype == np.float32), mca_seed, threads,
-                           out.ctypes.data_as(P(ctypes.c_double)))
+                           fix.ctypes.data_as(P(ctypes.c_uint8)), scheme,
+                           z[0].ctypes.data_as(dp), z[1].ctypes.data_as(dp),
+                           z[2].ctypes.data_as(dp) if len(z) == 3 else None, n,
+                           int(dtype == np.float32), mca_seed, threads, out.ctypes.data_as(dp))
     if rc != 0:
         raise ValueError("tm_evaluate: invalid argument")
     return out
@@ -125,7 +139,7 @@ def spread(p, opt_type, n_steps, seed, first, n, reference, mode=oracle.FULL_TRU
     round-to-nearest evaluation in ``dtype`` and ``members`` Monte-Carlo-
     arithmetic evaluations (seeds 1..members, so reproducible).
     ``reference``: the oracle's [n, >=8] derivatives of the same paths."""
-    z = oracle.normals(seed, first, n, n_steps)
+    z = inputs(p, opt_type, n_steps, seed, first, n, mode)
     ref = reference[:, :8]
     e = np.zeros_like(ref)
     for m in range(members + 1):

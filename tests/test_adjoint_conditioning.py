@@ -135,3 +135,42 @@ def test_fp64_spread_covers_the_oracles_own_rounding():
                         normals=z)
         s = np.fmax(s, np.abs(v[:, :8] - tan[:, :8]))
     assert (d <= np.maximum(plain, tb.FACTOR * s)).all()
+
+
+# ---------------------------------------------------------------------------
+# Andersen's QE scheme: the same bars for the QE adjoint.
+
+PQ = PB.replace(sigma=0.9, kappa=1.0, theta=0.05)  # Feller violated: exponential branch, zero mass
+
+
+@pytest.mark.parametrize("t", [0, 1, 2, 3])
+def test_qe_fp64_evaluation_reproduces_oracle(t):
+    """The QE evaluation is the oracle's QE tangent in binary64 (base
+    parameters, explicit fixings for the Asians)."""
+    N, n = 37, 1500
+    fix = (3, 10, 20, 37) if t >= 2 else None
+    tan = oracle.tangent(PB, t, N, 11, 0, n, oracle.QE, fix, threads=8)
+    ev = tb.evaluate(PB, t, N, 11, 0, n, oracle.QE, fix, dtype=np.float64)
+    rel = np.abs(ev[:, :8] - tan[:, :8]) / np.maximum(np.abs(tan[:, :8]), tb.floors(PB))
+    assert rel.max() < 1e-13, rel.max()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_qe_bar_covers_further_evaluations(dtype):
+    """Feller violated: sixteen further Monte-Carlo-arithmetic QE evaluations
+    land within the bar on every path and column away from the strike and from
+    a branch switch (margin 1e-4 in binary32, 1e-9 in binary64)."""
+    N, n = 100, 4196
+    for t in (0, 2):
+        tan = oracle.tangent(PQ, t, N, 5, 0, n, oracle.QE, threads=8)
+        bar = tb.bars(PQ, t, N, 5, 0, n, tan, oracle.QE, dtype=dtype)
+        z = tb.inputs(PQ, t, N, 5, 0, n, oracle.QE)
+        single = dtype == np.float32
+        ok = ~near_strike(PQ, t, N, 5, n, oracle.QE, tol=1e-5 if single else 1e-12)
+        ok &= tan[:, 8] >= (1e-4 if single else 1e-9)
+        assert ok.mean() > 0.9
+        for m in range(16):
+            ev = tb.evaluate(PQ, t, N, 5, 0, n, oracle.QE, dtype=dtype, mca_seed=9000 + m,
+                             normals=z)
+            worst = (np.abs(ev[:, :8] - tan[:, :8]) / bar)[ok].max()
+            assert worst <= 1.0, (t, m, worst)
