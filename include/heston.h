@@ -108,7 +108,8 @@ enum { HESTON_RNG_PHILOX = 0, HESTON_RNG_SOBOL_BRIDGE = 1 };
  * the call fail with HESTON_UNSUPPORTED.  The context keeps a scratch array of
  * 128 KiB per resident lane (min(n_paths rounded up to 256, 65536) lanes: up
  * to 8 GiB), counted against its HBM budget.
- * Adjoint calls, batches and the server use the Milstein schemes only. */
+ * Adjoint calls take the Milstein schemes with full truncation or absorption
+ * and QE; batches and the server use the Milstein schemes only. */
 enum {
     HESTON_FULL_TRUNCATION = 0,
     HESTON_ABSORPTION = 1,
@@ -322,8 +323,9 @@ heston_status heston_bump_revalue(heston_ctx *ctx, const heston_params *params,
  * Adjoint (reverse-mode) sensitivities of the price to
  * theta = (S0, v0, r, kappa, theta, sigma, rho): the exact derivative of every
  * path's discounted payoff (pathwise method, section "Pathwise method for
- * greeks estimation", carried through every Milstein step), averaged over
- * paths.  Philox normals only; |rho| < 1.
+ * greeks estimation", carried through every Milstein step, or through every
+ * step of Andersen's QE scheme with its branch decisions held fixed), averaged
+ * over paths.  Philox normals only; |rho| < 1.
  *
  * heston_adjoint_forward prices the option and writes the step states every
  * `every` steps (8 or 16) and the final state into the caller-owned DEVICE

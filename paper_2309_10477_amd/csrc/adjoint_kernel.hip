@@ -7,7 +7,9 @@
 // Philox normals (kept with the step's V+, sqrt(V+ dt) and fixing term in
 // registers), then runs the reverse recurrence of the Milstein step
 // (paper: algorithm "Milstein approximation under Heston model") with the
-// conventions d max(y,0)/dy = 1{y > 0} and d sqrt(V+ dt)/dV = 0 where V+ = 0.
+// conventions d max(y,0)/dy = 1{y > 0} and d sqrt(V+ dt)/dV = 0 where V+ = 0,
+// or, under Andersen's QE scheme (the paper's Future Work), the reverse
+// recurrence of the QE step with its branch decisions held fixed.
 // The payoff seeds follow the pathwise estimators of the paper's section
 // "Pathwise method for greeks estimation" (chain rule through S_T or the
 // discrete average); dS0 and dr reproduce the pathwise Delta and Rho.
@@ -21,7 +23,7 @@ namespace {
 // The forward pass of the adjoint: one path per lane, checkpoints of (x, V)
 // every `every` steps and the final (x_N, A), then the payoff and pathwise
 // estimators into FP64 block partials (price, Delta, Rho in the N_ACC layout).
-template <class R, bool ASIAN, bool FT>
+template <class R, bool ASIAN, int SC>
 __global__ __launch_bounds__(BLOCK) void adjoint_forward_kernel(const PriceLaunch L)
 {
     __shared__ double red[BLOCK / 64][N_ACC];
@@ -32,8 +34,12 @@ __global__ __launch_bounds__(BLOCK) void adjoint_forward_kernel(const PriceLaunc
     const PathConsts k = path_consts(L);
     R x, v, A, B;
     R *ck = reinterpret_cast<R *>(L.ckpt);
-    forward_path<R, ASIAN, FT>(k, L.first_path + rr, x, v, A, B, active ? ck : nullptr, np, rr,
-                               L.ckpt_every);
+    if constexpr (SC == 2)
+        forward_path_qe<R, ASIAN>(k, L.first_path + rr, x, v, A, B, active ? ck : nullptr, np, rr,
+                                  L.ckpt_every);
+    else
+        forward_path<R, ASIAN, SC == 0>(k, L.first_path + rr, x, v, A, B, active ? ck : nullptr,
+                                        np, rr, L.ckpt_every);
     double out[3];
     path_estimators<ASIAN>(k, (double)x, (double)A, (double)B, out[0], out[1], out[2]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -57,7 +63,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_forward_kernel(const PriceLaunc
     }
 }
 
-template <class R, bool ASIAN, bool FT, int SEG>
+template <class R, bool ASIAN, int SC, int SEG>
 __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const PriceLaunch L, double seed_grad,
                                                         double *__restrict__ per_path)
 {
@@ -68,8 +74,12 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const PriceLaunch L, dou
     const uint64_t rr = active ? row : 0;
     const PathConsts k = path_consts(L);
     double out[8];
-    adjoint_path<R, ASIAN, FT, SEG>(k, L.first_path + rr, reinterpret_cast<const R *>(L.ckpt), np,
-                                    rr, out);
+    if constexpr (SC == 2)
+        adjoint_path_qe<R, ASIAN, SEG>(k, L.first_path + rr, reinterpret_cast<const R *>(L.ckpt),
+                                       np, rr, out);
+    else
+        adjoint_path<R, ASIAN, SC == 0, SEG>(k, L.first_path + rr,
+                                             reinterpret_cast<const R *>(L.ckpt), np, rr, out);
 #pragma unroll
     for (int e = 1; e < 8; ++e)
         out[e] *= seed_grad;
@@ -99,44 +109,55 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const PriceLaunch L, dou
     }
 }
 
-template <class R, bool ASIAN, bool FT>
+template <class R, bool ASIAN, int SC>
 hipError_t launch_seg(const PriceLaunch &L, double g, double *pp, hipStream_t s)
 {
     const dim3 grid((uint32_t)((L.n_paths + BLOCK - 1) / BLOCK));
     if (L.ckpt_every == 8)
-        hipLaunchKernelGGL((adjoint_kernel<R, ASIAN, FT, 8>), grid, dim3(BLOCK), 0, s, L, g, pp);
+        hipLaunchKernelGGL((adjoint_kernel<R, ASIAN, SC, 8>), grid, dim3(BLOCK), 0, s, L, g, pp);
     else
-        hipLaunchKernelGGL((adjoint_kernel<R, ASIAN, FT, 16>), grid, dim3(BLOCK), 0, s, L, g, pp);
+        hipLaunchKernelGGL((adjoint_kernel<R, ASIAN, SC, 16>), grid, dim3(BLOCK), 0, s, L, g, pp);
     return hipGetLastError();
+}
+
+// L.scheme: 0 Milstein with full truncation, 1 with absorption, 2 QE.
+template <class R, bool ASIAN>
+hipError_t launch_sc(const PriceLaunch &L, double g, double *pp, hipStream_t s)
+{
+    return L.scheme == 0   ? launch_seg<R, ASIAN, 0>(L, g, pp, s)
+           : L.scheme == 1 ? launch_seg<R, ASIAN, 1>(L, g, pp, s)
+                           : launch_seg<R, ASIAN, 2>(L, g, pp, s);
 }
 
 template <class R>
 hipError_t launch_r(const PriceLaunch &L, double g, double *pp, hipStream_t s)
 {
-    const bool asian = L.opt_type >= 2;
-    if (asian)
-        return L.scheme == 0 ? launch_seg<R, true, true>(L, g, pp, s)
-                             : launch_seg<R, true, false>(L, g, pp, s);
-    return L.scheme == 0 ? launch_seg<R, false, true>(L, g, pp, s)
-                         : launch_seg<R, false, false>(L, g, pp, s);
+    return L.opt_type >= 2 ? launch_sc<R, true>(L, g, pp, s) : launch_sc<R, false>(L, g, pp, s);
+}
+
+template <class R, bool ASIAN, int SC> void launch_fwd_t(const PriceLaunch &L, hipStream_t s)
+{
+    const dim3 grid((uint32_t)((L.n_paths + BLOCK - 1) / BLOCK));
+    hipLaunchKernelGGL((adjoint_forward_kernel<R, ASIAN, SC>), grid, dim3(BLOCK), 0, s, L);
+}
+
+template <class R, bool ASIAN> void launch_fwd_sc(const PriceLaunch &L, hipStream_t s)
+{
+    if (L.scheme == 0)
+        launch_fwd_t<R, ASIAN, 0>(L, s);
+    else if (L.scheme == 1)
+        launch_fwd_t<R, ASIAN, 1>(L, s);
+    else
+        launch_fwd_t<R, ASIAN, 2>(L, s);
 }
 
 template <class R>
 hipError_t launch_fwd_r(const PriceLaunch &L, hipStream_t s)
 {
-    const dim3 grid((uint32_t)((L.n_paths + BLOCK - 1) / BLOCK));
-    const bool asian = L.opt_type >= 2;
-    if (asian) {
-        if (L.scheme == 0)
-            hipLaunchKernelGGL((adjoint_forward_kernel<R, true, true>), grid, dim3(BLOCK), 0, s, L);
-        else
-            hipLaunchKernelGGL((adjoint_forward_kernel<R, true, false>), grid, dim3(BLOCK), 0, s, L);
-    } else {
-        if (L.scheme == 0)
-            hipLaunchKernelGGL((adjoint_forward_kernel<R, false, true>), grid, dim3(BLOCK), 0, s, L);
-        else
-            hipLaunchKernelGGL((adjoint_forward_kernel<R, false, false>), grid, dim3(BLOCK), 0, s, L);
-    }
+    if (L.opt_type >= 2)
+        launch_fwd_sc<R, true>(L, s);
+    else
+        launch_fwd_sc<R, false>(L, s);
     return hipGetLastError();
 }
 

@@ -623,8 +623,11 @@ heston_status check_adjoint(const Request &q, uint32_t every, const void *ckpt, 
         return st;
     if (q.o.rng != HESTON_RNG_PHILOX)
         return fail(HESTON_UNSUPPORTED, "adjoint sensitivities need Philox normals");
-    if (q.o.scheme != HESTON_FULL_TRUNCATION && q.o.scheme != HESTON_ABSORPTION)
-        return fail(HESTON_UNSUPPORTED, "adjoint sensitivities follow the Milstein scheme");
+    if (q.o.scheme != HESTON_FULL_TRUNCATION && q.o.scheme != HESTON_ABSORPTION &&
+        q.o.scheme != HESTON_QE)
+        return fail(HESTON_UNSUPPORTED,
+                    "adjoint sensitivities follow the Milstein scheme (full truncation or "
+                    "absorption) or the QE scheme");
     if (q.o.control_variate != HESTON_CONTROL_NONE)
         return fail(HESTON_UNSUPPORTED, "adjoint calls take no control variate");
     if (q.type > HESTON_ASIAN_PUT)
