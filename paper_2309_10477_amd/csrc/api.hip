@@ -371,18 +371,21 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
                                hipMemcpyHostToDevice, c->stream));
         // Blocks of 64 consecutive points share their Gray-code bits >= 6; when the
         // launch's waves are block-aligned, the XOR of those bits' direction numbers
-        // is tabulated once per block and dimension, and the shifts, that table and
-        // the six low direction numbers of each node are laid out in the order the
+        // is tabulated once per block and dimension; the XOR of the direction
+        // numbers of the low six bits is tabulated once per node for each of their
+        // 64 values; and the shifts and both tables are laid out in the order the
         // bridge walk consumes its nodes, so the kernel addresses them by walk
         // position instead of through each op's node index.  The tables are an
         // accelerator only: without room for them under the context budget (or in
         // device memory) the kernel combines the direction numbers itself.
         L.sobol_hi = nullptr;
-        L.sobol_dir12 = nullptr;
+        L.sobol_low = nullptr;
         const uint32_t N = q.n_steps;
         const uint64_t n_blk = (M + 63) / 64, hi_bytes = n_blk * dims * 4;
-        const uint64_t extra = hi_bytes + (uint64_t)N * 4 + (uint64_t)N * 48;
-        const uint64_t held = c->sobol_hi.bytes + c->sobol_perm.bytes + c->sobol_dir12.bytes;
+        // the low-bit table [N+1][64][2] follows the [N][12] direction numbers it is built from
+        const uint64_t low_bytes = (uint64_t)N * 48 + ((uint64_t)N + 1) * 512;
+        const uint64_t extra = hi_bytes + (uint64_t)N * 4 + low_bytes;
+        const uint64_t held = c->sobol_hi.bytes + c->sobol_perm.bytes + c->sobol_low.bytes;
         const bool fits = !c->budget || c->in_use - held + extra + 3 * 4096 <= c->budget;
         std::vector<int32_t> node_of_pos;
         std::vector<uint32_t> dir12;
@@ -390,7 +393,7 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
         if (fast) {
             if ((st = reserve(c, c->sobol_hi, hi_bytes)) == HESTON_OK &&
                 (st = reserve(c, c->sobol_perm, (size_t)N * 4)) == HESTON_OK)
-                st = reserve(c, c->sobol_dir12, (size_t)N * 48);
+                st = reserve(c, c->sobol_low, (size_t)low_bytes);
             if (st == HESTON_OUT_OF_MEMORY || st == HESTON_OVER_BUDGET) {
                 g_last_error.clear();
                 fast = false;
@@ -411,15 +414,17 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
                             o.sobol_directions[(size_t)(2 * node_of_pos[pos] + mm) * 32 + b];
             HIP_TRY(hipMemcpyAsync(c->sobol_perm.ptr, node_of_pos.data(), (size_t)N * 4,
                                    hipMemcpyHostToDevice, c->stream));
-            HIP_TRY(hipMemcpyAsync(c->sobol_dir12.ptr, dir12.data(), (size_t)N * 48,
-                                   hipMemcpyHostToDevice, c->stream));
+            uint32_t *d12 = (uint32_t *)c->sobol_low.ptr, *low = d12 + (size_t)N * 12;
+            HIP_TRY(hipMemcpyAsync(d12, dir12.data(), (size_t)N * 48, hipMemcpyHostToDevice,
+                                   c->stream));
+            HIP_TRY(launch_sobol_low(d12, N, low, c->stream));
             const int32_t *perm = (const int32_t *)c->sobol_perm.ptr;
             HIP_TRY(launch_sobol_shifts(q.seed, perm, dims, R, (uint32_t *)c->sobol_shift.ptr,
                                         c->stream));
             HIP_TRY(launch_sobol_hi((const uint32_t *)c->sobol_dirs.ptr, perm, dims, (uint32_t)n_blk,
                                     (uint32_t *)c->sobol_hi.ptr, c->stream));
             L.sobol_hi = (const uint32_t *)c->sobol_hi.ptr;
-            L.sobol_dir12 = (const uint32_t *)c->sobol_dir12.ptr;
+            L.sobol_low = low;
         } else {
             HIP_TRY(launch_sobol_shifts(q.seed, nullptr, dims, R, (uint32_t *)c->sobol_shift.ptr,
                                         c->stream));
@@ -760,7 +765,7 @@ heston_status heston_ctx_destroy(heston_ctx *c)
         return fail(HESTON_INVALID_ARGUMENT, "ctx is NULL");
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift, &c->sobol_hi, &c->sobol_perm, &c->sobol_dir12,
+    for (DevBuf *b : {&c->partials, &c->rep_sums, &c->fix_bits, &c->sobol_dirs, &c->sobol_shift, &c->sobol_hi, &c->sobol_perm, &c->sobol_low,
                       &c->bridge_start, &c->bridge_ops, &c->pay, &c->bump_partials,
                       &c->geo_buf, &c->geo_partials, &c->geo_steps, &c->exact_scratch,
                       &c->reduce_tmp,

@@ -78,13 +78,14 @@ struct PriceLaunch {
     StepCoef base, tup, tdn;        // grids of T, T + hT, T - hT
     // quasi-random
     const uint32_t *sobol_dirs;     // device [2N][32]
-    const uint32_t *sobol_shift;    // device [R][2N] (position-ordered when sobol_dir12 is set)
+    const uint32_t *sobol_shift;    // device [R][2N] (position-ordered when sobol_low is set)
     const uint32_t *sobol_hi;       // device [ceil(M/64)][2N], position-ordered, or null: per
                                     // 64-point block, XOR of the direction numbers of Gray-code
                                     // bits >= 6
-    const uint32_t *sobol_dir12;    // device [N][12] or null: direction numbers 0..5 of the two
-                                    // dimensions of the node at each walk position (set exactly
-                                    // when sobol_hi is)
+    const uint32_t *sobol_low;      // device [N+1][64][2] or null: per walk position and value
+                                    // of a point's low six Gray-code bits, the XOR of the
+                                    // selected direction numbers 0..5 of the node's two
+                                    // dimensions (row N zero; set exactly when sobol_hi is)
     const int32_t *bridge_start;    // device [N+1]: ops of step j are [start[j], start[j+1])
     const BridgeOp *bridge_ops;     // device [N-1]
     double bridge_root_scale;       // sqrt(N)
@@ -275,5 +276,8 @@ hipError_t launch_sobol_hi(const uint32_t *dirs, const int32_t *perm, uint32_t d
 hipError_t launch_sobol_shifts(uint64_t seed, const int32_t *perm, uint32_t dims, uint32_t reps,
                                uint32_t *out,
                                hipStream_t stream);
+// Expands dir12 (device [N][12]: direction numbers 0..5 of the two dimensions
+// of the node at each walk position) into the [N+1][64][2] low-bit table.
+hipError_t launch_sobol_low(const uint32_t *dir12, uint32_t N, uint32_t *out, hipStream_t stream);
 
 } // namespace heston

@@ -57,12 +57,14 @@ __device__ __forceinline__ void sobol_normals(uint32_t x0, uint32_t x1, R &z0, R
 {
     if constexpr (sizeof(R) == 4) {
         // bit 29 marks the upper half: m is all ones there, and the mirror
-        // 0x3FFFFFFF - x of a 30-bit x is x with its 30 bits complemented;
-        // the sign is restored by flipping the float's sign bit (no selects)
+        // 0x3FFFFFFF - x of a 30-bit x is x with its 30 bits complemented
+        // (one bitop3: (m & 0x3FFFFFFF) ^ x); the sign is restored by flipping
+        // the float's sign bit (no selects)
         const uint32_t m0 = (uint32_t)__builtin_amdgcn_sbfe((int)x0, 29, 1);
         const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)x1, 29, 1);
         float a, b;
-        inv_normal_lower_bits2(x0 ^ (m0 & 0x3FFFFFFFu), x1 ^ (m1 & 0x3FFFFFFFu), a, b);
+        inv_normal_lower_bits2(__builtin_amdgcn_bitop3_b32(m0, 0x3FFFFFFFu, x0, 0x6A),
+                               __builtin_amdgcn_bitop3_b32(m1, 0x3FFFFFFFu, x1, 0x6A), a, b);
         z0 = __uint_as_float(__float_as_uint(a) ^ (m0 & 0x80000000u));
         z1 = __uint_as_float(__float_as_uint(b) ^ (m1 & 0x80000000u));
     } else {
@@ -469,9 +471,11 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
         // Two walks.  Fast (the launch's waves cover 64-point-aligned blocks and
         // the host built position-ordered tables): the node consumed at position
         // pos (0 = root, o + 1 = bridge op o) reads the wave's row of the
-        // per-block table, the replicate's shift and its six low direction
-        // numbers of both dimensions at addresses that depend only on pos, so
-        // an op's loads do not wait on the op record.  Otherwise dimensions are
+        // per-block table and the replicate's shift at addresses that depend only
+        // on pos, so an op's loads do not wait on the op record, and each lane
+        // reads the XOR of its low six Gray-code bits' direction numbers from the
+        // low-bit table (the wave's 64 lanes read one 512-byte row, which the
+        // next position's load fetches one op ahead).  Otherwise dimensions are
         // addressed through the op's node index and each lane combines the
         // direction numbers of its own Gray code.
         auto walk = [&](auto fast_tag) {
@@ -495,13 +499,22 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
                 }
                 return sobol_coord(L.sobol_dirs, d, g, nbits, shift[d]);
             };
-            // normals of the node at walk position pos (node index k)
+            // the lane's entry of the low-bit table at a walk position (row N is
+            // the zero pad that the last position's look-ahead reads)
+            const uint32_t g_lo = g & 63u;
+            auto low_at = [&](uint32_t pos) -> uint2 {
+                return reinterpret_cast<const uint2 *>(L.sobol_low + 128u * pos)[g_lo];
+            };
+            uint2 low_next = FAST ? low_at(0u) : uint2{0u, 0u};
+            // normals of the node at walk position pos (node index k); positions
+            // are consumed in order 0, 1, ..., N - 1
             auto node_normals = [&](uint32_t pos, int k, R &wa, R &wb) {
                 if constexpr (FAST) {
-                    const uint32_t *v6 = L.sobol_dir12 + 12u * pos;
+                    const uint2 lw = low_next;
+                    low_next = low_at(pos + 1u);
                     const uint32_t c = 2u * pos;
-                    sobol_normals<R>(shift[c] ^ hi_row[c] ^ sobol_low(v6, m),
-                                     shift[c + 1] ^ hi_row[c + 1] ^ sobol_low(v6 + 6, m), wa, wb);
+                    sobol_normals<R>(shift[c] ^ hi_row[c] ^ lw.x, shift[c + 1] ^ hi_row[c + 1] ^ lw.y,
+                                     wa, wb);
                 } else {
                     const uint32_t d = 2u * (uint32_t)k;
                     sobol_normals<R>(coord(d), coord(d + 1), wa, wb);
@@ -541,7 +554,7 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
                 step(j, za, zb);
             }
         };
-        if (L.sobol_dir12 != nullptr)
+        if (L.sobol_low != nullptr)
             walk(std::true_type{});
         else
             walk(std::false_type{});
@@ -857,6 +870,23 @@ __global__ void sobol_hi_kernel(const uint32_t *dirs, const int32_t *perm, uint3
     out[idx] = x;
 }
 
+// out[pos][l][h] = XOR of the direction numbers k < 6 of dimension h of the
+// node at walk position pos over the set bits k of l (l = a point's low six
+// Gray-code bits); row N is zero.
+__global__ void sobol_low_kernel(const uint32_t *dir12, uint32_t N, uint32_t *out)
+{
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (N + 1u) * 128u)
+        return;
+    const uint32_t pos = idx >> 7, l = (idx >> 1) & 63u, h = idx & 1u;
+    uint32_t x = 0;
+    if (pos < N)
+        for (uint32_t b = 0; b < 6; ++b)
+            if ((l >> b) & 1u)
+                x ^= dir12[pos * 12u + h * 6u + b];
+    out[idx] = x;
+}
+
 // Digital shifts of the Sobol replicates: shift[r][c] = top 30 bits of word 0
 // of Philox4x32-10(counter (d, r, 0, 1), key = seed), d = table_dim(c).
 __global__ void sobol_shift_kernel(uint64_t seed, const int32_t *perm, uint32_t dims, uint32_t reps,
@@ -935,6 +965,13 @@ hipError_t launch_sobol_hi(const uint32_t *dirs, const int32_t *perm, uint32_t d
     const uint64_t n = (uint64_t)dims * n_blk;
     hipLaunchKernelGGL(sobol_hi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
                        dirs, perm, dims, n_blk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sobol_low(const uint32_t *dir12, uint32_t N, uint32_t *out, hipStream_t stream)
+{
+    const uint32_t n = (N + 1u) * 128u;
+    hipLaunchKernelGGL(sobol_low_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, dir12, N, out);
     return hipGetLastError();
 }
 

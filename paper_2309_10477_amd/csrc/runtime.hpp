@@ -20,7 +20,7 @@ struct heston_ctx {
     hipStream_t stream = nullptr;
     uint64_t budget = 0; // 0 = unlimited
     uint64_t in_use = 0; // bytes held by the buffers below
-    DevBuf partials, rep_sums, fix_bits, sobol_dirs, sobol_shift, sobol_hi, sobol_perm, sobol_dir12;
+    DevBuf partials, rep_sums, fix_bits, sobol_dirs, sobol_shift, sobol_hi, sobol_perm, sobol_low;
     DevBuf bridge_start, bridge_ops;
     DevBuf pay, bump_partials, bump_sums, step_w;
     DevBuf geo_buf, geo_partials, geo_steps; // geometric-average control
