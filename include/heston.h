@@ -420,7 +420,9 @@ typedef struct heston_server_stats {
     uint64_t submitted, admitted, completed, queued, active;
     uint64_t launches;
     double path_steps;          /* path-steps simulated (items launched)           */
-    double busy_ms;             /* GPU time of the batched and fold kernels        */
+    double busy_ms;             /* time with at least one launch on the device (the
+                                   union of the launches' intervals; launches on
+                                   the three slots' streams may overlap)          */
     double p50_ms, p99_ms, mean_ms, max_ms; /* latency of completed requests       */
     uint64_t pool_bytes;        /* device memory for request states (the budget
                                    minus adjoint scratch and launch buffers)     */

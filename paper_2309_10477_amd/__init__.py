@@ -414,8 +414,12 @@ class Server:
         self.ctx = ctx
 
     def submit(self, **request) -> int:
+        return self.submit_request(make_request(**request))
+
+    def submit_request(self, q: CRequest) -> int:
+        """Submits a request built by make_request (for callers that build
+        their requests ahead of time)."""
         t = ctypes.c_uint64()
-        q = make_request(**request)
         check(lib().heston_submit(self.handle, ctypes.byref(q), ctypes.byref(t)))
         return t.value
 

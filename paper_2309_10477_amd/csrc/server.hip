@@ -9,8 +9,12 @@
 //      (a fair share of the per-launch work each), run the batched kernel over
 //      them, then the fold kernel, which extends every request's running sums
 //      item by item in item order and applies the stopping rule, and copies the
-//      folded states back to pinned memory; several launches may be queued on
-//      the stream, so new requests join while earlier ones run;
+//      folded states back to pinned memory.  Each of the three launch slots
+//      has its own stream and adjoint scratch, so a launch's kernels fill the
+//      compute units that the previous launch's last items leave idle; the
+//      folds run in launch order (each waits on the previous launch's fold),
+//      so new requests join while earlier ones run and every request's sums
+//      are extended in item order;
 //   3. complete: when a launch's event has fired, requests whose state says
 //      done get their result and latency recorded, and their memory is freed.
 // A request with an SE target is scheduled up to the items its observed SE
@@ -175,6 +179,9 @@ struct Req {
 };
 
 struct Launch {
+    hipStream_t stream = nullptr;
+    hipEvent_t fold_done = nullptr; // the fold of this slot's latest launch
+    unsigned char *scratch = nullptr; // this slot's adjoint scratch
     DevBuf opts, items, counter, tasks, out;
     heston::BatchOption *h_opts = nullptr;
     uint32_t *h_items = nullptr;
@@ -192,7 +199,6 @@ struct Launch {
 struct heston_server {
     heston_ctx *ctx = nullptr;
     heston_server_config cfg{};
-    hipStream_t stream = nullptr;
     DevBuf pool_buf, scratch;
     uint64_t scratch_per_block = 0;
     uint32_t grid_price = 0, grid_adj = 0;
@@ -200,6 +206,12 @@ struct heston_server {
     std::vector<Launch> launches; // ring
     size_t next_launch = 0;
     std::deque<size_t> inflight;  // launch indices in launch order
+    int last_fold = -1;           // slot of the latest launch (its fold orders the next)
+    // busy time: the union of the launches' device intervals, accumulated per
+    // busy period (from the first launch enqueued with none in flight to the
+    // end of the last one completed)
+    hipEvent_t span_start = nullptr;
+    double busy_closed_ms = 0, busy_open_ms = 0;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -216,6 +228,29 @@ struct heston_server {
 };
 
 namespace {
+
+constexpr size_t N_SLOTS = 3; // launch slots, each with its own stream
+
+// Waits for each slot's stream, then frees its buffers, events and stream.
+void release_launches(heston_server *s)
+{
+    for (auto &L : s->launches) {
+        if (L.stream)
+            (void)hipStreamSynchronize(L.stream);
+        for (DevBuf *b : {&L.opts, &L.items, &L.counter, &L.tasks, &L.out})
+            if (b->ptr)
+                (void)hipFree(b->ptr);
+        if (L.h_opts) (void)hipHostFree(L.h_opts);
+        if (L.h_items) (void)hipHostFree(L.h_items);
+        if (L.h_tasks) (void)hipHostFree(L.h_tasks);
+        if (L.h_out) (void)hipHostFree(L.h_out);
+        if (L.start) (void)hipEventDestroy(L.start);
+        if (L.end) (void)hipEventDestroy(L.end);
+        if (L.fold_done) (void)hipEventDestroy(L.fold_done);
+        if (L.stream) (void)hipStreamDestroy(L.stream);
+    }
+    s->launches.clear();
+}
 
 heston_status alloc_host(void **p, size_t bytes)
 {
@@ -345,7 +380,9 @@ heston_status launch_next(heston_server *s, bool &launched)
     }
     std::memcpy(L.h_items, w.item_opt.data(), w.item_opt.size() * 4);
     const uint32_t n_opts = (uint32_t)w.opts.size(), n_items = (uint32_t)w.item_opt.size();
-    hipStream_t sm = s->stream;
+    hipStream_t sm = L.stream;
+    if (s->inflight.empty())
+        HIP_TRY(hipEventRecord(s->span_start, sm));
     HIP_TRY(hipMemcpyAsync(L.opts.ptr, L.h_opts, n_opts * sizeof(heston::BatchOption),
                            hipMemcpyHostToDevice, sm));
     HIP_TRY(hipMemcpyAsync(L.items.ptr, L.h_items, n_items * 4, hipMemcpyHostToDevice, sm));
@@ -373,14 +410,18 @@ heston_status launch_next(heston_server *s, bool &launched)
         B.item_begin = w.n_price_items;
         B.item_end = n_items;
         B.counter = (uint32_t *)L.counter.ptr + 1;
-        B.scratch = (unsigned char *)s->scratch.ptr;
+        B.scratch = L.scratch;
         B.scratch_per_block = s->scratch_per_block;
         B.grid = std::min<uint32_t>(s->grid_adj, (n_items - w.n_price_items) * BATCH_UNITS);
         HIP_TRY(launch_batch(B, sm));
     }
+    if (s->last_fold >= 0)
+        HIP_TRY(hipStreamWaitEvent(sm, s->launches[(size_t)s->last_fold].fold_done, 0));
     hipLaunchKernelGGL(fold_kernel, dim3(n_opts), dim3(64), 0, sm, (const FoldTask *)L.tasks.ptr,
                        (ReqState *)L.out.ptr);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(L.fold_done, sm));
+    s->last_fold = (int)s->next_launch;
     HIP_TRY(hipMemcpyAsync(L.h_out, L.out.ptr, n_opts * sizeof(ReqState), hipMemcpyDeviceToHost,
                            sm));
     HIP_TRY(hipEventRecord(L.end, sm));
@@ -432,10 +473,12 @@ heston_status complete_ready(heston_server *s, bool block, bool &any)
             HIP_TRY(e);
         }
         block = false;
-        float ms = 0;
+        float ms = 0, span = 0;
         (void)hipEventElapsedTime(&ms, L.start, L.end);
+        (void)hipEventElapsedTime(&span, s->span_start, L.end);
         std::lock_guard<std::mutex> lk(s->mu);
-        s->stats.busy_ms += ms;
+        // launches complete in launch order; the busy period's extent so far
+        s->busy_open_ms = std::max(s->busy_open_ms, (double)span);
         for (size_t j = 0; j < L.reqs.size(); ++j) {
             Req *q = L.reqs[j];
             const ReqState &st = L.h_out[j];
@@ -473,6 +516,11 @@ heston_status complete_ready(heston_server *s, bool block, bool &any)
         L.busy = false;
         L.reqs.clear();
         s->inflight.pop_front();
+        if (s->inflight.empty()) {
+            s->busy_closed_ms += s->busy_open_ms;
+            s->busy_open_ms = 0;
+        }
+        s->stats.busy_ms = s->busy_closed_ms + s->busy_open_ms;
         any = true;
     }
     if (any)
@@ -559,20 +607,28 @@ heston_status heston_server_create(heston_ctx *ctx, const heston_server_config *
     s->ctx = ctx;
     s->cfg = c;
     auto bail = [&](heston_status st) {
-        if (s->stream) (void)hipStreamDestroy(s->stream);
+        release_launches(s);
+        if (s->span_start) (void)hipEventDestroy(s->span_start);
         if (s->pool_buf.ptr) (void)hipFree(s->pool_buf.ptr);
         if (s->scratch.ptr) (void)hipFree(s->scratch.ptr);
         delete s;
         return st;
     };
-    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
-        return bail(fail(HESTON_DEVICE_ERROR, "hipStreamCreate failed"));
+    s->launches.resize(N_SLOTS);
+    for (auto &L : s->launches)
+        if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreate(&L.start) != hipSuccess || hipEventCreate(&L.end) != hipSuccess ||
+            hipEventCreateWithFlags(&L.fold_done, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(HESTON_DEVICE_ERROR, "stream or event creation failed"));
+    if (hipEventCreate(&s->span_start) != hipSuccess)
+        return bail(fail(HESTON_DEVICE_ERROR, "hipEventCreate failed"));
     s->grid_price = batch_resident_blocks(c.precision, c.scheme, false);
     s->grid_adj = batch_resident_blocks(c.precision, c.scheme, true);
     if (s->grid_price == 0 || s->grid_adj == 0)
         return bail(fail(HESTON_DEVICE_ERROR, "occupancy query failed"));
     s->scratch_per_block = adjoint_scratch_per_block(c.max_steps, c.precision);
-    const uint64_t scratch_bytes = (uint64_t)s->grid_adj * s->scratch_per_block;
+    const uint64_t slot_scratch = (uint64_t)s->grid_adj * s->scratch_per_block;
+    const uint64_t scratch_bytes = N_SLOTS * slot_scratch;
     const uint64_t launch_bytes = 64ull << 20; // launch buffers, grown on demand
     if (c.hbm_budget_bytes < scratch_bytes + launch_bytes + 4096)
         return bail(fail(HESTON_OVER_BUDGET, "budget below the adjoint scratch (" +
@@ -585,10 +641,15 @@ heston_status heston_server_create(heston_ctx *ctx, const heston_server_config *
     s->scratch.bytes = scratch_bytes;
     s->pool_buf.bytes = pool_bytes;
     s->pool.init((unsigned char *)s->pool_buf.ptr, pool_bytes);
-    s->launches.resize(3);
-    for (auto &L : s->launches)
-        if (hipEventCreate(&L.start) != hipSuccess || hipEventCreate(&L.end) != hipSuccess)
-            return bail(fail(HESTON_DEVICE_ERROR, "hipEventCreate failed"));
+    for (size_t i = 0; i < s->launches.size(); ++i) {
+        Launch &L = s->launches[i];
+        L.scratch = (unsigned char *)s->scratch.ptr + i * slot_scratch;
+        // sized for the usual launch up front: growing a buffer later frees the
+        // old one, which waits for the whole device
+        heston_status st = grow_launch(L, std::min<uint32_t>(c.max_active, 4096), 1u << 16);
+        if (st != HESTON_OK)
+            return bail(st);
+    }
     s->engine = std::thread(engine_main, s);
     *out = s;
     return HESTON_OK;
@@ -603,21 +664,10 @@ heston_status heston_server_destroy(heston_server *s)
     if (s->engine.joinable())
         s->engine.join();
     DeviceGuard g(s->ctx->device);
-    (void)hipStreamSynchronize(s->stream);
-    for (auto &L : s->launches) {
-        for (DevBuf *b : {&L.opts, &L.items, &L.counter, &L.tasks, &L.out})
-            if (b->ptr)
-                (void)hipFree(b->ptr);
-        if (L.h_opts) (void)hipHostFree(L.h_opts);
-        if (L.h_items) (void)hipHostFree(L.h_items);
-        if (L.h_tasks) (void)hipHostFree(L.h_tasks);
-        if (L.h_out) (void)hipHostFree(L.h_out);
-        (void)hipEventDestroy(L.start);
-        (void)hipEventDestroy(L.end);
-    }
+    release_launches(s);
+    (void)hipEventDestroy(s->span_start);
     (void)hipFree(s->pool_buf.ptr);
     (void)hipFree(s->scratch.ptr);
-    (void)hipStreamDestroy(s->stream);
     for (Req *q : s->queue)
         delete q;
     for (Req *q : s->active)
