@@ -80,68 +80,88 @@ __device__ __forceinline__ double item_col(const double *records, uint32_t i, ui
     return t;
 }
 
-// One block per task: thread 0 walks the new items (price sums only) to find
-// where the stopping rule fires; then thread k < N_ACC adds column k of those
-// items in order.  An item's record is its BATCH_UNITS unit records added in
-// unit order.
-__global__ __launch_bounds__(64) void fold_kernel(const FoldTask *__restrict__ tasks,
-                                                  ReqState *__restrict__ out)
+// One block per task, the new items taken FOLD_CHUNK at a time: each thread
+// sums one item's unit records (in unit order) into LDS, then thread 0 walks
+// the chunk's price sums in item order to find where the stopping rule fires,
+// and thread k < N_ACC adds column k of the chunk's items up to there, in
+// item order.  The additions are those of a sequential walk, in its order.
+constexpr uint32_t FOLD_CHUNK = 64;
+
+__global__ __launch_bounds__(FOLD_CHUNK) void fold_kernel(const FoldTask *__restrict__ tasks,
+                                                          ReqState *__restrict__ out)
 {
-    __shared__ uint32_t s_stop;
+    __shared__ double s_item[FOLD_CHUNK][N_ACC];
+    __shared__ uint32_t s_take;
     __shared__ uint32_t s_done;
     const FoldTask t = tasks[blockIdx.x];
     ReqState *st = t.state;
+    const uint32_t tid = threadIdx.x;
     if (t.first) {
         double *raw = reinterpret_cast<double *>(st);
-        if (threadIdx.x < sizeof(ReqState) / 8)
-            raw[threadIdx.x] = 0.0;
+        if (tid < sizeof(ReqState) / 8)
+            raw[tid] = 0.0;
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             st->cap_paths = t.cap_paths;
             st->se_target = t.se_target;
             st->cap_items = t.cap_items;
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        uint32_t stop = t.upto;
-        uint32_t done = st->done;
-        if (!done) {
-            double s = st->sums[0], ss = st->sums[1];
-            for (uint32_t i = st->folded; i < t.upto; ++i) {
-                s += item_col(t.records, i, 0);
-                ss += item_col(t.records, i, 1);
-                const uint64_t paths = std::min<uint64_t>((uint64_t)(i + 1) * BATCH_CHUNK,
-                                                          st->cap_paths);
-                const double n = (double)paths, m = s / n;
-                const double var = paths > 1 ? fmax((ss - s * m) / (n - 1.0), 0.0) : 0.0;
-                const bool se_ok = st->se_target > 0 && i + 1 >= 2 && sqrt(var / n) <= st->se_target;
-                if (se_ok || i + 1 == st->cap_items) {
-                    stop = i + 1;
-                    done = 1;
-                    break;
+    if (!st->done) {
+        const uint32_t from = st->folded;
+        const uint64_t cap_paths = st->cap_paths;
+        const uint32_t cap_items = st->cap_items;
+        const double se_target = st->se_target;
+        double acc = tid < N_ACC ? st->sums[tid] : 0.0;
+        double s = st->sums[0], ss = st->sums[1];
+        uint32_t stop = t.upto, done = 0;
+        for (uint32_t base = from; base < t.upto; base += FOLD_CHUNK) {
+            const uint32_t n = min(FOLD_CHUNK, t.upto - base);
+            if (tid < n)
+                for (uint32_t k = 0; k < N_ACC; ++k)
+                    s_item[tid][k] = item_col(t.records, base + tid, k);
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t take = n, d = 0;
+                for (uint32_t j = 0; j < n; ++j) {
+                    const uint32_t i = base + j;
+                    s += s_item[j][0];
+                    ss += s_item[j][1];
+                    const uint64_t paths = std::min<uint64_t>((uint64_t)(i + 1) * BATCH_CHUNK, cap_paths);
+                    const double nn = (double)paths, m = s / nn;
+                    const double var = paths > 1 ? fmax((ss - s * m) / (nn - 1.0), 0.0) : 0.0;
+                    const bool se_ok = se_target > 0 && i + 1 >= 2 && sqrt(var / nn) <= se_target;
+                    if (se_ok || i + 1 == cap_items) {
+                        take = j + 1;
+                        d = 1;
+                        break;
+                    }
                 }
+                s_take = take;
+                s_done = d;
             }
-        } else {
-            stop = st->folded;
+            __syncthreads();
+            const uint32_t take = s_take;
+            if (tid < N_ACC)
+                for (uint32_t j = 0; j < take; ++j)
+                    acc += s_item[j][tid];
+            done = s_done;
+            __syncthreads(); // the chunk is read before the next one overwrites it
+            if (done) {
+                stop = base + take;
+                break;
+            }
         }
-        s_stop = stop;
-        s_done = done;
-    }
-    __syncthreads();
-    const uint32_t stop = s_stop;
-    if (threadIdx.x < N_ACC && !st->done) {
-        double acc = st->sums[threadIdx.x];
-        for (uint32_t i = st->folded; i < stop; ++i)
-            acc += item_col(t.records, i, threadIdx.x);
-        st->sums[threadIdx.x] = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && !st->done) {
-        st->folded = stop;
-        if (s_done) {
-            st->done = 1;
-            st->stop_items = stop;
+        if (tid < N_ACC)
+            st->sums[tid] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            st->folded = stop;
+            if (done) {
+                st->done = 1;
+                st->stop_items = stop;
+            }
         }
     }
     __syncthreads();
