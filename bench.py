@@ -19,6 +19,7 @@ loop's latency, and the CPU oracle timed on bounded samples of the workloads.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -28,6 +29,14 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+# HIP maps a process's streams onto GPU_MAX_HW_QUEUES hardware queues (4 by
+# default) and streams that share one run one after the other.  The serving
+# engine overlaps launches on three streams of its own beside the context's
+# (and the control variate's side stream), so this process asks for eight;
+# set before anything initialises HIP.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 from workloads import ASIAN_LARGE, BASE, QMC_REPLICATES  # noqa: E402
 
@@ -280,14 +289,36 @@ def portfolio_batch(ctx, hm, torch):
             "path_steps_per_s": ps / wall, "kernel_path_steps_per_s": ps / (ms * 1e-3)}
 
 
+def variant_steps(ctx, torch, wl, opts, warmup=20, reps=30):
+    """The timed step's workload under other options: `warmup` untimed calls
+    (the clocks settle over some tens of milliseconds after a change of
+    kernel), then `reps` timed calls.  Returns (last result, wall ms per call,
+    [path-kernel ms per call])."""
+    for _ in range(warmup):
+        ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ks = []
+    for _ in range(reps):
+        r = ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, opts)
+        ks.append(r["device_ms"])
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t1) / reps * 1e3, ks
+
+
 def serving(ctx, hm, torch, n_measured=2000, n_warm=100):
     """Continuous batching: requests (50/50 European/Asian, calls/puts, path cap
     2^U[12,22], steps U{50..1000}, Heston parameters as the portfolio's, price
-    + seven adjoint sensitivities to a price SE of 0.1) arrive as a Poisson
-    stream at 0.5 and 0.8 of the saturated request rate, which is measured
-    first from a burst.  Latency = heston_submit to completion.  Path-steps
-    count the paths each result uses (whole 1024-path items up to the one that
-    met the target); the scheduled figure adds the items computed past it."""
+    + seven adjoint sensitivities to a price SE of 0.1).  Saturation: after a
+    burst of n_warm requests on the same server, n_measured requests submitted
+    at once (built beforehand); its rate is the completed work over the time
+    from the first submission to the last completion (as the server timed it),
+    drain included.  Then,
+    still on that server (a serving engine runs warm), Poisson streams at 0.5
+    and 0.8 of the saturated request rate, n_warm + n_measured requests each,
+    latency (heston_submit to completion) of the last n_measured.  Path-steps count the paths each result uses (whole 1024-path
+    items up to the one that met the target); the scheduled figure adds the
+    items computed past it."""
     from workloads import request_stream
 
     def to_reqs(rs):
@@ -295,45 +326,63 @@ def serving(ctx, hm, torch, n_measured=2000, n_warm=100):
                      n_paths=int(rs.path_cap[i]), seed=int(rs.seed[i]), want=hm.WANT_ADJOINT,
                      se_target=rs.se_target) for i in range(len(rs.params))]
 
-    def run(reqs, arrivals):
-        srv = hm.Server(ctx, precision=hm.FP32, max_steps=1000)
+    def run(srv, reqs, arrivals):
+        # The run ends at the last completion as the server saw it (each
+        # request's submission time plus its latency), so that a pause of this
+        # client while it collects results does not count; the cyclic garbage
+        # collector stays off meanwhile, so it cannot delay submissions.
+        built = [hm.make_request(**q) for q in reqs]
+        st0 = srv.stats()
+        gc.collect()
+        gc.disable()
         try:
             t0 = time.perf_counter()
-            tickets = []
-            for q, a in zip(reqs, arrivals):
+            tickets, t_sub = [], []
+            for c, a in zip(built, arrivals):
                 while time.perf_counter() - t0 < a:
                     pass
-                tickets.append(srv.submit(**q))
+                t_sub.append(time.perf_counter() - t0)
+                tickets.append(srv.submit_request(c))
             res = [srv.wait(t, 300_000) for t in tickets]
-            wall = time.perf_counter() - t0
-            st = srv.stats()
         finally:
-            srv.close()
+            gc.enable()
+        wall = max(ts + r["latency_ms"] * 1e-3 for ts, r in zip(t_sub, res))
+        st = {k: v - st0[k] for k, v in srv.stats().items()}
         return res, wall, st
 
     def useful(reqs, res):
         # path-steps behind the results: each request's paths used x its steps
         return float(sum(r["n_paths"] * q["n_steps"] for q, r in zip(reqs, res)))
 
-    burst = to_reqs(request_stream(400, 1.0, seed=5))
-    res, wall, st = run(burst, np.zeros(400))
-    mu = 400 / wall
-    out = {"saturated_requests_per_s": mu,
-           "saturated_path_steps_per_s": useful(burst, res) / wall,
-           "saturated_scheduled_path_steps_per_s": st["path_steps"] / wall,
-           "mean_paths_used": float(np.mean([r["n_paths"] for r in res]))}
-    for frac in (0.5, 0.8):
-        rs = request_stream(n_warm + n_measured, frac * mu, seed=6)
-        reqs = to_reqs(rs)
-        res, wall, st = run(reqs, rs.arrival_s)
+    def load_record(rate, reqs, res, wall, st):
+        # latency of the last n_measured requests; rates over the whole stream
         lat = np.array([r["latency_ms"] for r in res[n_warm:]])
-        out[f"load_{frac}"] = {
-            "arrival_rate_per_s": frac * mu, "requests": n_measured,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "throughput_requests_per_s": len(res) / wall,
-            "path_steps_per_s": useful(reqs, res) / wall,
-            "scheduled_path_steps_per_s": st["path_steps"] / wall, "launches": st["launches"],
-            "gpu_busy_frac": st["busy_ms"] * 1e-3 / wall}
+        return {"arrival_rate_per_s": rate, "requests": n_measured,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "throughput_requests_per_s": len(res) / wall,
+                "path_steps_per_s": useful(reqs, res) / wall,
+                "scheduled_path_steps_per_s": st["path_steps"] / wall,
+                "launches": st["launches"], "gpu_busy_frac": st["busy_ms"] * 1e-3 / wall}
+
+    srv = hm.Server(ctx, precision=hm.FP32, max_steps=1000)
+    try:
+        warm = to_reqs(request_stream(n_warm, 1.0, seed=4))
+        run(srv, warm, np.zeros(n_warm))
+        burst = to_reqs(request_stream(n_measured, 1.0, seed=5))
+        res, wall, st = run(srv, burst, np.zeros(n_measured))
+        mu = n_measured / wall
+        out = {"saturated_requests": n_measured, "saturated_requests_per_s": mu,
+               "saturated_path_steps_per_s": useful(burst, res) / wall,
+               "saturated_scheduled_path_steps_per_s": st["path_steps"] / wall,
+               "saturated_gpu_busy_frac": st["busy_ms"] * 1e-3 / wall,
+               "mean_paths_used": float(np.mean([r["n_paths"] for r in res]))}
+        for frac in (0.5, 0.8):
+            rs = request_stream(n_warm + n_measured, frac * mu, seed=6)
+            reqs = to_reqs(rs)
+            res, wall, st = run(srv, reqs, rs.arrival_s)
+            out[f"load_{frac}"] = load_record(frac * mu, reqs, res, wall, st)
+    finally:
+        srv.close()
     return out
 
 
@@ -403,32 +452,14 @@ def main():
     if "qmc" in legs:
         # the same step with Sobol + Brownian-bridge normals (16 shifted replicates)
         qopts = hm.Options(precision=hm.FP32, rng=hm.SOBOL_BRIDGE, qmc_replicates=QMC_REPLICATES)
-        for _ in range(2):
-            ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, qopts)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        qk = []
-        for _ in range(5):
-            rq = ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, qopts)
-            qk.append(rq["device_ms"])
-        torch.cuda.synchronize()
-        q_ms = (time.perf_counter() - t1) / 5 * 1e3
+        rq, q_ms, qk = variant_steps(ctx, torch, wl, qopts)
         out["qmc_sobol_bridge"] = {"value": path_steps / (q_ms * 1e-3), "unit": "path-steps/s",
                                    "ms_per_step": q_ms, "kernel_ms": float(np.mean(qk)),
                                    "price": rq["price"], "replicates": QMC_REPLICATES}
     if "qe" in legs:
         # the same step under Andersen's QE scheme (one Philox block per step)
         eopts = hm.Options(precision=hm.FP32, scheme=hm.QE)
-        for _ in range(2):
-            ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, eopts)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ek = []
-        for _ in range(5):
-            re_ = ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, eopts)
-            ek.append(re_["device_ms"])
-        torch.cuda.synchronize()
-        e_ms = (time.perf_counter() - t1) / 5 * 1e3
+        re_, e_ms, ek = variant_steps(ctx, torch, wl, eopts)
         out["qe_scheme"] = {"value": path_steps / (e_ms * 1e-3), "unit": "path-steps/s",
                             "ms_per_step": e_ms, "kernel_ms": float(np.mean(ek)),
                             "price": re_["price"]}
@@ -436,16 +467,7 @@ def main():
         # the same step with the geometric-average control variate on the price:
         # wall time includes the control's device-side transform price
         copts = hm.Options(precision=hm.FP32, control_variate=hm.CONTROL_GEOMETRIC)
-        for _ in range(2):
-            ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, copts)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ck = []
-        for _ in range(5):
-            rc = ctx.price_greeks(wl.params, wl.opt_type, wl.n_paths, wl.n_steps, wl.seed, copts)
-            ck.append(rc["device_ms"])
-        torch.cuda.synchronize()
-        c_ms = (time.perf_counter() - t1) / 5 * 1e3
+        rc, c_ms, ck = variant_steps(ctx, torch, wl, copts)
         vrf = (rc["price"][1] / rc["cv_price"][1]) ** 2
         out["geometric_control_variate"] = {
             "value": path_steps / (c_ms * 1e-3), "unit": "path-steps/s", "ms_per_step": c_ms,
