@@ -215,28 +215,30 @@ __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 // of the quadratic branch, uv the uniform of the exponential branch.
 // psi = s2 / m^2 <= 3/2 takes the scaled squared normal a (b + zv)^2, else V'
 // is 0 with probability p = (psi-1)/(psi+1) and exponential above it.
-// qe_pre gives m, s2 and psi; qe_post evaluates a branch only when some lane
-// of the wave takes it (quad, expo: wave-uniform votes over all scenarios).
+// qe_pre gives m, s2 and the branch (psi <= 3/2 tested as s2 <= 3/2 m^2, no
+// division); qe_post evaluates a branch only when some lane of the wave takes
+// it (quad, expo: wave-uniform votes over all scenarios), psi itself only in
+// the exponential branch.
 // Away from zero variance every lane takes the quadratic branch, so whole
 // waves skip the exponential one and its logarithm; each lane still selects
 // by its own psi, so the result is that of evaluating both.
 template <class R> struct QEPre {
-    R m, s2, psi;
+    R m, s2;
+    bool quad; // psi = s2 / m^2 <= 3/2
 };
 
 template <class R> __device__ __forceinline__ QEPre<R> qe_pre(R w, const QEGrid<R> &g)
 {
     const R m = w * g.E + g.mth;
     const R s2 = w * g.cs1 + g.cs0;
-    const R rm = fast_rcp(m);
-    return QEPre<R>{m, s2, s2 * rm * rm};
+    return QEPre<R>{m, s2, s2 <= R(1.5) * (m * m)};
 }
 
 template <class R>
 __device__ __forceinline__ void qe_post(R &y, R &w, const QEGrid<R> &g, const QEPre<R> &q, R z1l,
                                         R zv, R uv, bool quad, bool expo)
 {
-    const R m = q.m, s2 = q.s2, psi = q.psi;
+    const R m = q.m, s2 = q.s2;
     R wq = R(0), we = R(0);
     if (quad) {
         const R inv = R(2) * m * m * fast_rcp(s2);
@@ -250,11 +252,13 @@ __device__ __forceinline__ void qe_post(R &y, R &w, const QEGrid<R> &g, const QE
         // p = (psi - 1) / (psi + 1), 1 - p = 2 / (psi + 1), 1 / beta = m (psi + 1) / 2;
         // uv <= p is tested as uv (psi + 1) <= psi - 1 and ln((1 - p) / (1 - uv))
         // as -ln((psi + 1)(1 - uv) / 2)
+        const R rm = fast_rcp(m);
+        const R psi = s2 * rm * rm;
         const R pp1 = psi + R(1);
         we = uv * pp1 <= psi - R(1) ? R(0)
                                     : -(R(0.5) * m * pp1) * fast_log(R(0.5) * pp1 * (R(1) - uv));
     }
-    const R wn = psi <= R(1.5) ? wq : we;
+    const R wn = q.quad ? wq : we;
     y = y + g.k0 + g.k1 * w + g.k2 * wn + fast_sqrt(g.k3 * w + g.k4 * wn) * z1l;
     w = wn;
 }
@@ -404,15 +408,15 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
             const R z1l = zs * log2e;
             const QEPre<R> q0 = qe_pre<R>(w, qb);
             QEPre<R> q1{}, q2{}, q3{}, q4{};
-            bool lo = q0.psi <= R(1.5), hi = !lo;
+            bool lo = q0.quad, hi = !lo;
             if constexpr (BUMPS) {
                 q1 = qe_pre<R>(wv0, qb);
                 q2 = qe_pre<R>(wv1, qb);
                 q3 = qe_pre<R>(wt0, qu);
                 q4 = qe_pre<R>(wt1, qd);
-                for (const R ps : {q1.psi, q2.psi, q3.psi, q4.psi}) {
-                    lo = lo || ps <= R(1.5);
-                    hi = hi || !(ps <= R(1.5));
+                for (const bool qd_ : {q1.quad, q2.quad, q3.quad, q4.quad}) {
+                    lo = lo || qd_;
+                    hi = hi || !qd_;
                 }
             }
             const bool quad = any_lane(lo), expo = any_lane(hi);
