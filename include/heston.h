@@ -109,7 +109,7 @@ enum { HESTON_RNG_PHILOX = 0, HESTON_RNG_SOBOL_BRIDGE = 1 };
  * 128 KiB per resident lane (min(n_paths rounded up to 256, 65536) lanes: up
  * to 8 GiB), counted against its HBM budget.
  * Adjoint calls take the Milstein schemes with full truncation or absorption
- * and QE; batches and the server use the Milstein schemes only. */
+ * and QE; so do batches and the server. */
 enum {
     HESTON_FULL_TRUNCATION = 0,
     HESTON_ABSORPTION = 1,
@@ -378,7 +378,9 @@ typedef struct heston_request {
 } heston_request;
 
 /* Prices reqs[0..n-1] (host array) into out[0..n-1] (host array).  opts
- * (nullable) supplies precision and truncation; Philox normals only; opts
+ * (nullable) supplies precision and scheme (HESTON_FULL_TRUNCATION,
+ * HESTON_ABSORPTION or HESTON_QE; under QE the adjoint differentiates the
+ * steps with their branches held fixed); Philox normals only; opts
  * fixing_steps must be NULL.  Blocks until done; device_ms (nullable) gets the
  * GPU time of the batched kernels.  Errors: INVALID_ARGUMENT (any request
  * invalid; nothing is priced), UNSUPPORTED, OVER_BUDGET / OUT_OF_MEMORY
@@ -407,7 +409,8 @@ typedef struct heston_server heston_server;
 typedef struct heston_server_config {
     uint32_t struct_size;       /* sizeof(heston_server_config)                    */
     int32_t precision;          /* HESTON_FP32 (default) or HESTON_FP64            */
-    int32_t scheme;             /* HESTON_FULL_TRUNCATION (default) / ABSORPTION   */
+    int32_t scheme;             /* HESTON_FULL_TRUNCATION (default), ABSORPTION or
+                                   QE                                             */
     uint32_t max_active;        /* admitted requests at once (default 4096)        */
     uint32_t max_steps;         /* largest n_steps accepted (default 2048)         */
     uint32_t reserved;

@@ -213,8 +213,10 @@ extern "C" heston_status heston_price_batch(heston_ctx *c, const heston_request 
         o = *opts;
     if (o.rng != HESTON_RNG_PHILOX)
         return fail(HESTON_UNSUPPORTED, "batches use Philox normals");
-    if (o.scheme != HESTON_FULL_TRUNCATION && o.scheme != HESTON_ABSORPTION)
-        return fail(HESTON_UNSUPPORTED, "batches use the Milstein scheme");
+    if (o.scheme != HESTON_FULL_TRUNCATION && o.scheme != HESTON_ABSORPTION &&
+        o.scheme != HESTON_QE)
+        return fail(HESTON_UNSUPPORTED,
+                    "batches use the Milstein scheme (full truncation or absorption) or QE");
     if (o.fixing_steps)
         return fail(HESTON_INVALID_ARGUMENT, "batched Asians fix at every step; fixing_steps must be NULL");
     if (o.control_variate != HESTON_CONTROL_NONE)

@@ -13,9 +13,10 @@
 // is bitwise the same alone or in any batch.
 //
 // Per item and path: the Milstein path of the paper's algorithm "Milstein
-// approximation under Heston model" in R, payoff and pathwise estimators in
-// FP64; in adjoint mode the path's forward pass also stores checkpoints in
-// the workgroup's scratch slot and the reverse sweep follows immediately.
+// approximation under Heston model" (or Andersen's QE step, the paper's Future
+// Work) in R, payoff and pathwise estimators in FP64; in adjoint mode the
+// path's forward pass also stores checkpoints in the workgroup's scratch slot
+// and the reverse sweep follows immediately.
 #include "device_math.hpp"
 #include "internal.hpp"
 #include "path_step.hpp"
@@ -25,7 +26,8 @@ namespace {
 
 // Runs unit `sub` of an item (its paths sub BLOCK .. sub BLOCK + BLOCK-1);
 // the wave sums go to the LDS row red[wave].
-template <class R, bool ASIAN, bool FT, bool ADJ>
+// SC: 0 Milstein with full truncation, 1 with absorption, 2 QE.
+template <class R, bool ASIAN, int SC, bool ADJ>
 __device__ __forceinline__ void run_unit_paths(const BatchOption &op, uint64_t chunk, uint32_t sub,
                                                R *scratch, double (*red)[N_ACC])
 {
@@ -36,12 +38,22 @@ __device__ __forceinline__ void run_unit_paths(const BatchOption &op, uint64_t c
     double out[8];
     if constexpr (ADJ) {
         R x, v, A, B;
-        forward_path<R, ASIAN, FT>(op.k, p, x, v, A, B, scratch, BLOCK, tid, BATCH_CKPT_EVERY);
-        __threadfence_block();
-        adjoint_path<R, ASIAN, FT, BATCH_CKPT_EVERY>(op.k, p, scratch, BLOCK, tid, out);
+        if constexpr (SC == 2) {
+            forward_path_qe<R, ASIAN>(op.k, p, x, v, A, B, scratch, BLOCK, tid, BATCH_CKPT_EVERY);
+            __threadfence_block();
+            adjoint_path_qe<R, ASIAN, BATCH_CKPT_EVERY>(op.k, p, scratch, BLOCK, tid, out);
+        } else {
+            forward_path<R, ASIAN, SC == 0>(op.k, p, x, v, A, B, scratch, BLOCK, tid,
+                                            BATCH_CKPT_EVERY);
+            __threadfence_block();
+            adjoint_path<R, ASIAN, SC == 0, BATCH_CKPT_EVERY>(op.k, p, scratch, BLOCK, tid, out);
+        }
     } else {
         R x, v, A, B;
-        forward_path<R, ASIAN, FT>(op.k, p, x, v, A, B, nullptr, 0, 0, 2);
+        if constexpr (SC == 2)
+            forward_path_qe<R, ASIAN>(op.k, p, x, v, A, B, nullptr, 0, 0, 2);
+        else
+            forward_path<R, ASIAN, SC == 0>(op.k, p, x, v, A, B, nullptr, 0, 0, 2);
         path_estimators<ASIAN>(op.k, (double)x, (double)A, (double)B, out[0], out[1], out[2]);
 #pragma unroll
         for (int e = 3; e < 8; ++e)
@@ -59,17 +71,18 @@ __device__ __forceinline__ void run_unit_paths(const BatchOption &op, uint64_t c
     }
 }
 
-// Adjoint items run the forward pass and the reverse sweep back to back, and
-// the single-precision kernel would hold 141 VGPRs (three waves per SIMD);
-// bounded to four waves per SIMD (128 VGPRs) the compiler spills a few
-// per-item values, reloaded once per item or sub-block, never inside the step
-// loops.
-template <class R, bool ADJ> struct BatchWaves {
-    static constexpr int value = (ADJ && sizeof(R) == 4) ? 4 : 1;
+// Adjoint units run the forward pass and the reverse sweep back to back; left
+// to itself the single-precision kernel held up to 141 VGPRs (three waves per
+// SIMD); bounded to four waves per SIMD it fits in 128 or fewer (114-115 for
+// the Milstein schemes in the current build), without spills.
+// The QE reverse sweep keeps more per step (Zs, the branch input) and would
+// spill at four waves; it is bounded to three.
+template <class R, int SC, bool ADJ> struct BatchWaves {
+    static constexpr int value = (ADJ && sizeof(R) == 4) ? (SC == 2 ? 3 : 4) : 1;
 };
 
-template <class R, bool FT, bool ADJ>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BatchWaves<R, ADJ>::value)))
+template <class R, int SC, bool ADJ>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BatchWaves<R, SC, ADJ>::value)))
 void batch_kernel(const BatchOption *__restrict__ opts,
                                                       const uint32_t *__restrict__ item_opt,
                                                       uint32_t item_begin, uint32_t item_end,
@@ -95,9 +108,9 @@ void batch_kernel(const BatchOption *__restrict__ opts,
         const uint32_t i = g - op.first_item;
         const uint64_t chunk = op.chunk_base + i;
         if (op.k.type >= 2)
-            run_unit_paths<R, true, FT, ADJ>(op, chunk, sub, my_scratch, red);
+            run_unit_paths<R, true, SC, ADJ>(op, chunk, sub, my_scratch, red);
         else
-            run_unit_paths<R, false, FT, ADJ>(op, chunk, sub, my_scratch, red);
+            run_unit_paths<R, false, SC, ADJ>(op, chunk, sub, my_scratch, red);
         __syncthreads();
         if (threadIdx.x < N_ACC) {
             double t = 0.0;
@@ -133,50 +146,59 @@ __global__ __launch_bounds__(BLOCK) void batch_reduce_kernel(const BatchOption *
     }
 }
 
-template <class R, bool FT, bool ADJ> int resident_blocks()
+template <class R, int SC, bool ADJ> int resident_blocks()
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<R, FT, ADJ>, BLOCK, 0) !=
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<R, SC, ADJ>, BLOCK, 0) !=
             hipSuccess)
         return 0;
     return cus * (per_cu > 0 ? per_cu : 1);
 }
 
-template <class R, bool FT, bool ADJ>
+template <class R, int SC, bool ADJ>
 hipError_t launch_t(const BatchLaunch &B, hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_kernel<R, FT, ADJ>), dim3(B.grid), dim3(BLOCK), 0, s, B.opts,
+    hipLaunchKernelGGL((batch_kernel<R, SC, ADJ>), dim3(B.grid), dim3(BLOCK), 0, s, B.opts,
                        B.item_opt, B.item_begin, B.item_end, B.counter, B.scratch,
                        B.scratch_per_block);
     return hipGetLastError();
 }
 
-template <class R, bool FT> int resident_r(bool adj)
+template <class R, int SC> int resident_sc(bool adj)
 {
-    return adj ? resident_blocks<R, FT, true>() : resident_blocks<R, FT, false>();
+    return adj ? resident_blocks<R, SC, true>() : resident_blocks<R, SC, false>();
 }
 
-template <class R, bool FT> hipError_t launch_r(const BatchLaunch &B, hipStream_t s)
+template <class R> int resident_r(int scheme, bool adj)
 {
-    return B.adjoint ? launch_t<R, FT, true>(B, s) : launch_t<R, FT, false>(B, s);
+    return scheme == 0 ? resident_sc<R, 0>(adj) : scheme == 1 ? resident_sc<R, 1>(adj)
+                                                              : resident_sc<R, 2>(adj);
+}
+
+template <class R, int SC> hipError_t launch_sc(const BatchLaunch &B, hipStream_t s)
+{
+    return B.adjoint ? launch_t<R, SC, true>(B, s) : launch_t<R, SC, false>(B, s);
+}
+
+template <class R> hipError_t launch_r(const BatchLaunch &B, hipStream_t s)
+{
+    return B.scheme == 0 ? launch_sc<R, 0>(B, s) : B.scheme == 1 ? launch_sc<R, 1>(B, s)
+                                                                 : launch_sc<R, 2>(B, s);
 }
 
 } // namespace
 
+// scheme: HESTON_FULL_TRUNCATION (0), HESTON_ABSORPTION (1) or HESTON_QE (2).
 int batch_resident_blocks(int precision, int scheme, bool adjoint)
 {
-    if (precision == 0)
-        return scheme == 0 ? resident_r<double, true>(adjoint) : resident_r<double, false>(adjoint);
-    return scheme == 0 ? resident_r<float, true>(adjoint) : resident_r<float, false>(adjoint);
+    return precision == 0 ? resident_r<double>(scheme, adjoint) : resident_r<float>(scheme, adjoint);
 }
 
 hipError_t launch_batch(const BatchLaunch &B, hipStream_t s)
 {
-    if (B.precision == 0)
-        return B.scheme == 0 ? launch_r<double, true>(B, s) : launch_r<double, false>(B, s);
-    return B.scheme == 0 ? launch_r<float, true>(B, s) : launch_r<float, false>(B, s);
+    return B.precision == 0 ? launch_r<double>(B, s) : launch_r<float>(B, s);
 }
 
 hipError_t launch_batch_reduce(const BatchLaunch &B, double *sums, hipStream_t s)

@@ -619,7 +619,8 @@ heston_status heston_server_create(heston_ctx *ctx, const heston_server_config *
         c = *cfg;
     }
     if ((c.precision != HESTON_FP32 && c.precision != HESTON_FP64) ||
-        (c.scheme != HESTON_FULL_TRUNCATION && c.scheme != HESTON_ABSORPTION) || c.max_active == 0 ||
+        (c.scheme != HESTON_FULL_TRUNCATION && c.scheme != HESTON_ABSORPTION &&
+         c.scheme != HESTON_QE) || c.max_active == 0 ||
         c.max_steps == 0 || c.max_steps > (1u << 20) || c.launch_path_steps == 0)
         return fail(HESTON_INVALID_ARGUMENT, "invalid server configuration");
     DeviceGuard g(ctx->device);

@@ -205,3 +205,114 @@ def test_invalid_batch_requests(hm, ctx):
             ctx.price_batch([good[1], q])
     with pytest.raises(hm.HestonError):
         ctx.price_batch(good, hm.Options(fixings=(1, 2)))
+    for scheme in (hm.EULER_FULL_TRUNCATION, hm.PARTIAL_TRUNCATION, hm.EXACT):
+        with pytest.raises(hm.HestonError):
+            ctx.price_batch(good, hm.Options(scheme=scheme))
+
+
+# ---------------------------------------------------------------------------
+# Andersen's QE scheme in the batched kernel (the paper's Future Work).  A QE
+# path whose branch decision lies within the oracle's margin (column 8 of its
+# QE tangent) can take the other branch in the kernel's arithmetic and then
+# has an entirely different V'; the mean-level bars cannot absorb that, so
+# the oracle comparisons use requests with no path within 1e-9 (FP64) or
+# 1e-4 (FP32) of a branch switch, which each test checks; bitwise alone/mix
+# agreement (and, in tests/test_gpu_server.py, served/batch agreement) covers
+# all requests.
+
+def qe_margin(q):
+    p = oracle.Params(**q["params"])
+    return oracle.simulate_qe(p, q["type"], q["n_steps"], q["seed"], 0, q["n_paths"],
+                              threads=8)[1]
+
+
+def qe_clear(reqs, thr):
+    return [q for q in reqs if qe_margin(q).min() >= thr]
+
+
+def test_batch_qe_fp64_matches_oracle(hm, ctx):
+    reqs = qe_clear(mixed_requests(), 1e-9)
+    assert len(reqs) >= 8
+    res, _ = ctx.price_batch(reqs, hm.Options(precision=hm.FP64, scheme=hm.QE,
+                                              greeks=hm.GREEKS_PATHWISE))
+    for q, r in zip(reqs, res):
+        ref, _ = oracle_estimates(q, oracle.QE)
+        for k in ("price", "pw_delta", "pw_rho"):
+            assert r[k][0] == pytest.approx(ref[k][0], rel=1e-10, abs=1e-12), (q, k)
+            assert r[k][1] == pytest.approx(ref[k][1], rel=1e-6, abs=1e-12), (q, k)
+
+
+def qe_adjoint_bars(q, prec):
+    p = oracle.Params(**q["params"])
+    tan = oracle.tangent(p, q["type"], q["n_steps"], q["seed"], 0, q["n_paths"], oracle.QE,
+                         threads=8)
+    per = tb.bars(p, q["type"], q["n_steps"], q["seed"], 0, q["n_paths"], tan, oracle.QE,
+                  dtype=np.float64 if prec == 0 else np.float32)
+    m, se = oracle.mean_se(tan[:, :8])
+    return m, se, per.mean(axis=0), tan[:, 8]
+
+
+def test_batch_qe_adjoint_fp64_matches_oracle(hm, ctx):
+    reqs = mixed_requests(want=hm.WANT_ADJOINT)
+    res, _ = ctx.price_batch(reqs, hm.Options(precision=hm.FP64, scheme=hm.QE,
+                                              greeks=hm.GREEKS_PATHWISE))
+    checked = 0
+    for q, r in zip(reqs, res):
+        m, se, bar, margin = qe_adjoint_bars(q, 0)
+        if margin.min() < 1e-9:
+            continue
+        checked += 1
+        assert r["price"][0] == pytest.approx(m[0], rel=1e-10, abs=1e-12)
+        for k in range(7):
+            assert abs(r["adj"][k][0] - m[1 + k]) <= bar[1 + k], (q, k)
+            assert r["adj"][k][1] == pytest.approx(se[1 + k], rel=1e-4, abs=1e-12)
+    assert checked >= 8
+
+
+def qe_fp32_requests(n=6, want=2):
+    """Requests at the base parameters (Feller holds, so no QE step comes near
+    a branch switch), 50..400 steps, every option type."""
+    g = np.random.default_rng(13)
+    base = dict(workloads.BASE)
+    out = []
+    for i in range(n):
+        p = dict(base, K=float(g.uniform(85, 115)), T=float(g.uniform(0.5, 2.0)))
+        out.append(dict(params=p, type=i % 4, n_steps=int(g.integers(50, 401)),
+                        n_paths=int(1500 + 611 * i), seed=int(g.integers(0, 2**62)), want=want))
+    return out
+
+
+def test_batch_qe_fp32_adjoint_matches_oracle(hm, ctx):
+    reqs = qe_fp32_requests()
+    res, _ = ctx.price_batch(reqs, hm.Options(precision=hm.FP32, scheme=hm.QE,
+                                              greeks=hm.GREEKS_PATHWISE))
+    for q, r in zip(reqs, res):
+        m, se, bar, margin = qe_adjoint_bars(q, 1)
+        assert margin.min() >= 1e-4, q
+        assert abs(r["price"][0] - m[0]) <= bar[0], q
+        for k in range(7):
+            assert abs(r["adj"][k][0] - m[1 + k]) <= bar[1 + k], (q, k, r["adj"][k], m[1 + k])
+
+
+def test_batch_qe_fp32_price_mode_matches_oracle(hm, ctx):
+    """Price mode: the price and the pathwise Delta and Rho (the tangent's
+    d/dS0 and d/dr) within the same mean-level bars."""
+    reqs = qe_fp32_requests(want=1)
+    res, _ = ctx.price_batch(reqs, hm.Options(precision=hm.FP32, scheme=hm.QE,
+                                              greeks=hm.GREEKS_PATHWISE))
+    for q, r in zip(reqs, res):
+        m, se, bar, margin = qe_adjoint_bars(q, 1)
+        assert margin.min() >= 1e-4, q
+        for k, col in (("price", 0), ("pw_delta", 1), ("pw_rho", 3)):
+            assert abs(r[k][0] - m[col]) <= bar[col], (q, k, r[k], m[col], bar[col])
+
+
+@pytest.mark.parametrize("want", [1, 2])
+def test_batch_qe_alone_and_in_the_mix_are_bitwise_equal(hm, ctx, want):
+    reqs = mixed_requests(want=want)
+    opts = hm.Options(precision=hm.FP32, scheme=hm.QE, greeks=hm.GREEKS_PATHWISE)
+    mix, _ = ctx.price_batch(reqs, opts)
+    for i in (1, 4, 10):
+        alone, _ = ctx.price_batch([reqs[i]], opts)
+        for k in ("price", "pw_delta", "pw_rho", "adj"):
+            assert alone[0][k] == mix[i][k], (i, k)

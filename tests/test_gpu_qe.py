@@ -178,7 +178,8 @@ def test_qe_rejections(hm, ctx):
         ctx.price_greeks(PB.__dict__, 0, 64, 4, 1,
                          hm.Options(scheme=hm.QE, rng=hm.SOBOL_BRIDGE, qmc_replicates=2))
     assert e.value.status == -5
+    # batches take QE (tests/test_gpu_batch.py), with the same parameter checks
     with pytest.raises(hm.HestonError) as e:
-        ctx.price_batch([dict(params=PB.__dict__, type=0, n_steps=4, n_paths=100, seed=1, want=1)],
-                        qe)
-    assert e.value.status == -5
+        ctx.price_batch([dict(params=PB.replace(sigma=0.0).__dict__, type=0, n_steps=4,
+                              n_paths=100, seed=1, want=1)], qe)
+    assert e.value.status == -1

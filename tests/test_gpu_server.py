@@ -178,3 +178,22 @@ def test_poll_and_errors(hm, ctx):
             srv.submit(**dict(q, want=0))
     finally:
         srv.close()
+
+
+def test_served_qe_matches_batch(hm, ctx):
+    """A server running Andersen's QE scheme: served requests (price and
+    adjoint modes, FP32 and FP64) equal the batch API's results up to the
+    order in which the FP64 unit records are added (the batch API's QE
+    results are checked against the oracle in tests/test_gpu_batch.py)."""
+    for prec in (hm.FP32, hm.FP64):
+        for want in (1, 2):
+            reqs = requests(8, want=want, seed=31)
+            res, _ = serve(hm, ctx, reqs, precision=prec, scheme=hm.QE)
+            bat, _ = ctx.price_batch(reqs, hm.Options(precision=prec, scheme=hm.QE,
+                                                      greeks=hm.GREEKS_PATHWISE))
+            for q, r, b in zip(reqs, res, bat):
+                assert r["n_paths"] == q["n_paths"]
+                for k in ("price", "pw_delta", "pw_rho"):
+                    assert r[k][0] == pytest.approx(b[k][0], rel=1e-12, abs=1e-13), (prec, want, k)
+                for k in range(7 if want == 2 else 0):
+                    assert r["adj"][k][0] == pytest.approx(b["adj"][k][0], rel=1e-12, abs=1e-13)
