@@ -193,6 +193,25 @@ def test_adjoint_large_sampled(hm, ctx):
         torch.cuda.empty_cache()
 
 
+def test_adjoint_qe_large_sampled(hm, ctx):
+    """QE at the adjoint benchmark's size (2^22 paths x 365 steps, FP32,
+    checkpoints every 16 steps): sampled windows against the oracle's QE
+    tangent under the QE bars, and the reduced gradients against the per-path
+    values."""
+    import torch
+    n, N, seed = 1 << 22, 365, 42
+    for opt_type in (0, 2):
+        price, grads, d = adjoint_per_path(hm, ctx, PB, opt_type, n, N, seed, 1, 16, hm.QE)
+        for first in (0, n // 3, n - 600):
+            check_against_tangent(d[first:first + 600], PB, opt_type, N, seed, first, 600, 1, 2,
+                                  None)
+        for k in range(7):
+            m, se = oracle.mean_se(d[:, 1 + k])
+            assert grads[k][0] == pytest.approx(m, rel=1e-9, abs=1e-12)
+        del d
+        torch.cuda.empty_cache()
+
+
 def test_adjoint_against_analytic(hm, ctx):
     """FP32, 2^21 paths: the seven European-call sensitivities at 400 steps
     within 3 SE of the characteristic-function values, plus the discretisation
