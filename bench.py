@@ -309,16 +309,16 @@ def variant_steps(ctx, torch, wl, opts, warmup=20, reps=30):
 def serving(ctx, hm, torch, n_measured=2000, n_warm=100):
     """Continuous batching: requests (50/50 European/Asian, calls/puts, path cap
     2^U[12,22], steps U{50..1000}, Heston parameters as the portfolio's, price
-    + seven adjoint sensitivities to a price SE of 0.1).  Saturation: after a
-    burst of n_warm requests on the same server, n_measured requests submitted
-    at once (built beforehand); its rate is the completed work over the time
-    from the first submission to the last completion (as the server timed it),
-    drain included.  Then,
-    still on that server (a serving engine runs warm), Poisson streams at 0.5
-    and 0.8 of the saturated request rate, n_warm + n_measured requests each,
-    latency (heston_submit to completion) of the last n_measured.  Path-steps count the paths each result uses (whole 1024-path
-    items up to the one that met the target); the scheduled figure adds the
-    items computed past it."""
+    + seven adjoint sensitivities to a price SE of 0.1).  Saturation: after an
+    untimed burst of n_measured other requests on the same server, n_measured
+    requests submitted at once (built beforehand); its rate is the completed
+    work over the time from the first submission to the last completion (as
+    the server timed it), drain included.  Then, still on that server (a
+    serving engine runs warm), Poisson streams at 0.5 and 0.8 of the saturated
+    request rate, n_warm + n_measured requests each, latency (heston_submit to
+    completion) of the last n_measured.  Path-steps count the paths each
+    result uses (whole 1024-path items up to the one that met the target); the
+    scheduled figure adds the items computed past it."""
     from workloads import request_stream
 
     def to_reqs(rs):
@@ -366,8 +366,11 @@ def serving(ctx, hm, torch, n_measured=2000, n_warm=100):
 
     srv = hm.Server(ctx, precision=hm.FP32, max_steps=1000)
     try:
-        warm = to_reqs(request_stream(n_warm, 1.0, seed=4))
-        run(srv, warm, np.zeros(n_warm))
+        # the first burst in a process runs 10-15% slower than later ones (the
+        # runtime's pools grow over it), so the untimed warm-up burst has the
+        # measured burst's size
+        warm = to_reqs(request_stream(n_measured, 1.0, seed=4))
+        run(srv, warm, np.zeros(n_measured))
         burst = to_reqs(request_stream(n_measured, 1.0, seed=5))
         res, wall, st = run(srv, burst, np.zeros(n_measured))
         mu = n_measured / wall
