@@ -106,8 +106,8 @@ enum { HESTON_RNG_PHILOX = 0, HESTON_RNG_SOBOL_BRIDGE = 1 };
  * Philox blocks with counter (step, lo32 path, hi32 path, 5 + 256 k).  Paths
  * whose draws leave the sampler's numerical range (see exact_kernel.hip) make
  * the call fail with HESTON_UNSUPPORTED.  The context keeps a scratch array of
- * 128 KiB per resident lane (min(n_paths rounded up to 256, 65536) lanes: up
- * to 8 GiB), counted against its HBM budget.
+ * 128 KiB per resident lane (min(n_paths rounded up to 256, 131072) lanes: up
+ * to 16 GiB), counted against its HBM budget.
  * Adjoint calls take the Milstein schemes with full truncation or absorption
  * and QE; so do batches and the server. */
 enum {

@@ -112,7 +112,8 @@ constexpr uint32_t EXACT_COUNTER_TAG = 5u;      // fourth Philox counter word, p
 constexpr int EXACT_MAX_GAMMA_ATTEMPTS = 64;
 constexpr double EXACT_MAX_POISSON_MEAN = 700.0;
 constexpr uint32_t EXACT_MAX_GRID = 16384;      // characteristic-function points per draw
-constexpr uint32_t EXACT_MAX_LANES = 65536;     // resident lanes (one wave per SIMD)
+constexpr uint32_t EXACT_MAX_LANES = 131072;    // resident lanes (two waves per SIMD:
+                                                 // the kernel holds 244 VGPRs)
 constexpr int EXACT_REC = N_ACC + 2;            // partial record: estimator sums, failures, pad
 struct ExactLaunch {
     double S0, K, r, T, v0, kappa, theta, sigma, rho, rho_bar;
