@@ -11,7 +11,9 @@ library; there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import operator
 import os
+import struct
 from dataclasses import dataclass
 
 import numpy as np
@@ -195,6 +197,23 @@ class Options:
 class _OptsHolder:
     """A COpts plus the host arrays it points to (kept alive for the call)."""
 
+    _cache: dict = {}
+
+    @classmethod
+    def get(cls, o: Options, n_steps: int) -> "_OptsHolder":
+        """The holder for these option values (built once per distinct set; the
+        C library only reads it)."""
+        fix = None if o.fixings is None else tuple(int(k) for k in o.fixings)
+        key = (o.precision, o.rng, o.scheme, o.greeks, o.qmc_replicates, fix, o.bump_S0_rel,
+               o.bump_v0_rel, o.bump_r_abs, o.bump_T_abs, o.control_variate,
+               n_steps if o.rng == SOBOL_BRIDGE else 0)
+        h = cls._cache.get(key)
+        if h is None:
+            if len(cls._cache) >= 64:
+                cls._cache.clear()
+            h = cls._cache[key] = cls(o, n_steps)
+        return h
+
     def __init__(self, o: Options, n_steps: int):
         self.c = COpts()
         check(lib().heston_default_opts(ctypes.byref(self.c)))
@@ -223,9 +242,15 @@ def _directions_cached(dims: int) -> np.ndarray:
     return _dir_cache[dims]
 
 
+_param_values = operator.itemgetter(*PARAM_NAMES)
+
+
 def _cparams(params) -> CParams:
     if isinstance(params, dict):
-        return CParams(*(float(params[n]) for n in PARAM_NAMES))
+        try:
+            return CParams(*_param_values(params))
+        except TypeError:  # values ctypes does not take as they are (e.g. numpy integers)
+            return CParams(*(float(params[n]) for n in PARAM_NAMES))
     return CParams(*(float(getattr(params, n)) for n in PARAM_NAMES))
 
 
@@ -259,7 +284,7 @@ class Context:
     def price_greeks(self, params, opt_type: int, n_paths: int, n_steps: int, seed: int,
                      opts: Options | None = None) -> dict:
         """{estimator: (value, std_err)} plus 'device_ms', 'latency_ms' and 'n_paths'."""
-        o = _OptsHolder(opts or Options(), n_steps)
+        o = _OptsHolder.get(opts or Options(), n_steps)
         res = CResult()
         cp = _cparams(params)
         check(lib().heston_price_greeks_ex(self.handle, ctypes.byref(cp), opt_type, n_paths,
@@ -354,20 +379,24 @@ def ckpt_bytes(n_paths: int, n_steps: int, every: int = 16, precision: int = FP3
     return int(lib().heston_adjoint_ckpt_bytes(n_paths, n_steps, every, precision))
 
 
+# heston_result as one record: 8 + 7 estimates (value, std_err), n_paths,
+# valid_mask, reserved, device_ms, cv_price, cv_beta, cv_mean, latency_ms.
+_RESULT = struct.Struct("<30dQIId2dddd")
+
+
 def _result_dict(res: CResult) -> dict:
-    out = {}
-    for n in EST_NAMES:
-        e = getattr(res, n)
-        out[n] = (e.value, e.std_err)
-    out["adj"] = [(res.adj[k].value, res.adj[k].std_err) for k in range(7)]
-    out["valid_mask"] = res.valid_mask
-    out["n_paths"] = res.n_paths
-    out["device_ms"] = res.device_ms
-    out["latency_ms"] = res.latency_ms
-    if res.valid_mask & VALID_CONTROL:
-        out["cv_price"] = (res.cv_price.value, res.cv_price.std_err)
-        out["cv_beta"] = res.cv_beta
-        out["cv_mean"] = res.cv_mean
+    v = _RESULT.unpack_from(bytes(res))
+    out = dict(zip(EST_NAMES, zip(v[0:16:2], v[1:16:2])))
+    out["adj"] = list(zip(v[16:30:2], v[17:30:2]))
+    n_paths, mask, _, device_ms, cv_value, cv_se, cv_beta, cv_mean, latency_ms = v[30:]
+    out["valid_mask"] = mask
+    out["n_paths"] = n_paths
+    out["device_ms"] = device_ms
+    out["latency_ms"] = latency_ms
+    if mask & VALID_CONTROL:
+        out["cv_price"] = (cv_value, cv_se)
+        out["cv_beta"] = cv_beta
+        out["cv_mean"] = cv_mean
     return out
 
 

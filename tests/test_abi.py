@@ -95,3 +95,43 @@ def test_enum_constants_match_binding():
             hm.REFLECTION, hm.EXACT, hm.EXACT_MAX_STEPS, hm.GREEKS_PATHWISE, hm.GREEKS_BUMP_FUSED,
             hm.GREEKS_BUMP_PLAIN]
     assert got == want
+
+
+def test_result_unpacking_matches_the_struct():
+    """The binding reads heston_result as one packed record: every field set to
+    a distinct value comes back under its own name."""
+    import paper_2309_10477_amd as hm
+    r = hm.CResult()
+    v = 1.0
+    for n in hm.EST_NAMES + ("cv_price",):
+        getattr(r, n).value, getattr(r, n).std_err = v, v + 0.5
+        v += 1.0
+    for k in range(7):
+        r.adj[k].value, r.adj[k].std_err = v, v + 0.5
+        v += 1.0
+    r.n_paths, r.valid_mask, r.reserved = 12345678901, hm.VALID_CONTROL | hm.VALID_ADJOINT, 7
+    r.device_ms, r.cv_beta, r.cv_mean, r.latency_ms = 101.5, 102.5, 103.5, 104.5
+    d = hm._result_dict(r)
+    for n in hm.EST_NAMES:
+        assert d[n] == (getattr(r, n).value, getattr(r, n).std_err), n
+    assert d["adj"] == [(r.adj[k].value, r.adj[k].std_err) for k in range(7)]
+    assert d["cv_price"] == (r.cv_price.value, r.cv_price.std_err)
+    assert (d["n_paths"], d["valid_mask"]) == (r.n_paths, r.valid_mask)
+    assert (d["device_ms"], d["cv_beta"], d["cv_mean"], d["latency_ms"]) == (101.5, 102.5, 103.5,
+                                                                               104.5)
+    r.valid_mask = hm.VALID_PRICE
+    assert "cv_price" not in hm._result_dict(r)
+
+
+def test_options_holder_cache_keys_on_every_field():
+    import paper_2309_10477_amd as hm
+    a = hm._OptsHolder.get(hm.Options(precision=hm.FP32), 50)
+    assert hm._OptsHolder.get(hm.Options(precision=hm.FP32), 50) is a
+    for other in (hm.Options(precision=hm.FP64), hm.Options(precision=hm.FP32, bump_T_abs=0.01),
+                  hm.Options(precision=hm.FP32, fixings=[5, 10]),
+                  hm.Options(precision=hm.FP32, scheme=hm.QE)):
+        b = hm._OptsHolder.get(other, 50)
+        assert b is not a
+        assert (b.c.precision, b.c.scheme, b.c.bump_T_abs, b.c.n_fixings) == (
+            other.precision, other.scheme, other.bump_T_abs,
+            0 if other.fixings is None else len(other.fixings))
