@@ -330,9 +330,27 @@ void plan_launch(const Request &q, uint64_t first, uint64_t count, PriceLaunch &
         L.fix_step_sum = 0.5 * (double)q.n_steps * ((double)q.n_steps + 1.0);
 }
 
+// Few FP64 paths with fused bumps (Philox, Milstein or Euler, European or
+// arithmetic Asian, no control) take one scenario per lane: at most about one
+// wave per SIMD, and a wave's work per step roughly halves (price_kernel SPLIT).
+bool split_layout(const Request &q, const PriceLaunch &L, uint64_t count)
+{
+    return q.o.precision == HESTON_FP64 && L.rng == HESTON_RNG_PHILOX && L.bumps && !L.cv &&
+           (L.scheme == 0 || L.scheme == 1) && q.type <= HESTON_ASIAN_PUT &&
+           count <= SPLIT_MAX_PATHS;
+}
+// Paths per block of the launch.
+uint64_t paths_per_block(const PriceLaunch &L)
+{
+    return L.split ? (uint64_t)(BLOCK / 64) * SPLIT_PATHS_PER_WAVE : BLOCK;
+}
+
 // Builds the launch description of paths [first, first+count) of request q
 // and uploads its tables into the context's scratch.  Does not launch.
-heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t count, PriceLaunch &L)
+// allow_split: the caller launches the path kernel for estimates only (no
+// dumps or per-path payoffs), so the launch may take the split layout.
+heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t count, PriceLaunch &L,
+                   bool allow_split = false)
 {
     const heston_opts &o = q.o;
     plan_launch(q, first, count, L);
@@ -451,8 +469,10 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
     }
     L.paths_per_rep = M;
     const uint64_t span = std::min<uint64_t>(count, M);
-    L.blocks_per_rep = (uint32_t)((span + BLOCK - 1) / BLOCK);
-    if ((uint64_t)L.blocks_per_rep * BLOCK < span || L.blocks_per_rep > 0x7FFFFFFFu)
+    L.split = allow_split && split_layout(q, L, count);
+    const uint64_t per_block = paths_per_block(L);
+    L.blocks_per_rep = (uint32_t)((span + per_block - 1) / per_block);
+    if ((uint64_t)L.blocks_per_rep * per_block < span || L.blocks_per_rep > 0x7FFFFFFFu)
         return fail(HESTON_UNSUPPORTED, "too many paths for one launch");
     heston_status st;
     const size_t W = (size_t)L.acc_width();
@@ -1045,7 +1065,7 @@ static heston_status price_greeks_impl(heston_ctx *c, const heston_params *param
         return HESTON_OK;
     }
     PriceLaunch L;
-    if ((st = plan(c, q, 0, n_paths, L)) != HESTON_OK)
+    if ((st = plan(c, q, 0, n_paths, L, true)) != HESTON_OK)
         return st;
     L.dump = nullptr;
     GeoControl gc;
@@ -1304,7 +1324,10 @@ heston_status heston_price_greeks_noalloc(const heston_params *params, heston_op
     L.rep0 = 0;
     L.n_reps = 1;
     L.paths_per_rep = n_paths;
-    L.blocks_per_rep = (uint32_t)std::min<uint64_t>((n_paths + BLOCK - 1) / BLOCK, 0xFFFFFFFFu);
+    L.split = split_layout(q, L, n_paths); // as the context call lays it out
+    const uint64_t per_block = paths_per_block(L);
+    L.blocks_per_rep =
+        (uint32_t)std::min<uint64_t>((n_paths + per_block - 1) / per_block, 0xFFFFFFFFu);
     // scratch layout: fixing bitmask, fixing weights, block partials,
     // first-level sums, estimator sums (each 256-byte aligned)
     const bool asian = q.type >= 2;
@@ -1319,7 +1342,7 @@ heston_status heston_price_greeks_noalloc(const heston_params *params, heston_op
     const size_t o_tmp = align256(o_part + (size_t)L.blocks_per_rep * W * 8);
     const size_t o_sums = align256(o_tmp + (chunks > 1 ? chunks * W * 8 : 0));
     const size_t need = o_sums + W * 8;
-    if ((uint64_t)L.blocks_per_rep * BLOCK < n_paths || need > HESTON_NOALLOC_SCRATCH_BYTES)
+    if ((uint64_t)L.blocks_per_rep * per_block < n_paths || need > HESTON_NOALLOC_SCRATCH_BYTES)
         return fail(HESTON_OVER_BUDGET,
                     "the request needs " + std::to_string(need) +
                         " bytes of device scratch, more than the no-allocation call's fixed " +

@@ -33,6 +33,10 @@ constexpr int MAX_BRIDGE_DEPTH = 24;
 constexpr uint32_t QE_COUNTER_TAG = 4u;
 // Largest per-block Sobol table (ceil(M/64) x 2N words) built for a launch;
 // above it the kernel combines the high direction numbers itself.
+// Scenario-split layout of small FP64 bump launches (price_kernel SPLIT):
+// paths per wave, and the largest launch it is used for (about one wave per SIMD).
+constexpr uint32_t SPLIT_PATHS_PER_WAVE = 12;
+constexpr uint64_t SPLIT_MAX_PATHS = 12288;
 constexpr uint64_t SOBOL_HI_MAX_BYTES = 256ull << 20;
 // Fixing weights per step j (fixing time t = (j+1) dt): e^{rt}, t e^{rt},
 // t^2 e^{rt}, t^3 e^{rt} on the base grid, e^{rt} on the T + hT and T - hT grids.
@@ -61,6 +65,8 @@ struct PriceLaunch {
     int precision;     // 0 fp64, 1 fp32
     int rng;           // 0 Philox, 1 Sobol + bridge
     bool bumps;        // fused bump scenarios
+    bool split;        // one scenario per lane (price_kernel's SPLIT layout; blocks_per_rep
+                       // then counts blocks of BLOCK / 64 * SPLIT_PATHS_PER_WAVE paths)
     bool cv;           // arithmetic Asian with the geometric control (records N_ACC_CV wide)
     uint32_t n_steps;
     uint32_t n_fix;                 // number of fixing dates

@@ -273,11 +273,23 @@ __device__ __forceinline__ bool any_lane(bool c)
 // Single-precision QE asks for six waves per SIMD: left to itself the compiler
 // spends 140-147 VGPRs on it (three waves); bounded, it fits in 76 without
 // spilling and runs 4% faster.  The other variants keep the default.
-template <class R, int RNG, int AV, bool BUMPS, int SCH>
+// SPLIT (small FP64 launches with fused bumps, Milstein, Philox, European or
+// arithmetic Asian): each lane runs one scenario of one path -- lane l of a
+// wave takes path l / 5 of the wave's SPLIT_PATHS_PER_WAVE and scenario l % 5
+// (base, v0+, v0-, T+, T-; lanes 60-63 idle) -- with that scenario's grid,
+// initial variance and fixing weight, and the base lane gathers the other four
+// final states before the payoffs.  Every scenario takes the same operations
+// as in the fused layout, so the per-path values are the same; a wave does
+// about half the work per step of the fused layout's, which pays only while
+// the launch has at most about one wave per SIMD.
+template <class R, int RNG, int AV, bool BUMPS, int SCH, bool SPLIT = false>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void price_kernel(
     const PriceLaunch L)
 {
+    static_assert(!SPLIT || (sizeof(R) == 8 && RNG == 0 && BUMPS && (AV == 0 || AV == 1) &&
+                             (SCH == 0 || SCH == 1)),
+                  "scenario-split layout: FP64, Philox, fused bumps, Milstein, no geometric average");
     // AV: 0 European, 1 arithmetic average, 2 geometric average over the
     // fixings, 3 arithmetic average with the geometric one as its control.
     // SCH: 0 Milstein with full truncation, 1 Milstein with absorption, 2 QE,
@@ -294,8 +306,11 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
     const uint64_t lo = L.first_path > rep_lo ? L.first_path : rep_lo;
     const uint64_t end = L.first_path + L.n_paths;
     const uint64_t hi = end < rep_lo + M ? end : rep_lo + M;
-    const uint64_t p = lo + (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const bool active = p < hi;
+    const uint32_t scen = SPLIT ? (threadIdx.x & 63) % 5 : 0; // scenario of the lane (SPLIT)
+    const uint64_t p = SPLIT ? lo + (uint64_t)blockIdx.x * (BLOCK / 64 * SPLIT_PATHS_PER_WAVE) +
+                                   (threadIdx.x >> 6) * SPLIT_PATHS_PER_WAVE + (threadIdx.x & 63) / 5
+                             : lo + (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+    bool active = p < hi && (!SPLIT || (threadIdx.x & 63) < 5 * SPLIT_PATHS_PER_WAVE);
 
     const uint32_t N = L.n_steps;
     const Grid<R> gb = grid<R>(L.base, L.sigma);
@@ -311,6 +326,12 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
     if constexpr (BUMPS) {
         gu = grid<R>(L.tup, L.sigma);
         gd = grid<R>(L.tdn, L.sigma);
+    }
+    // SPLIT: the lane's scenario grid and initial w (as the fused layout's states start)
+    Grid<R> gs = gb;
+    if constexpr (SPLIT) {
+        gs = scen == 3 ? gu : scen == 4 ? gd : gb;
+        w = scen == 1 ? wv0 : scen == 2 ? wv1 : scen == 3 ? wt0 : scen == 4 ? wt1 : w;
     }
     QEGrid<R> qb{}, qu{}, qd{};
     if constexpr (SCH == 2) {
@@ -334,6 +355,17 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
                     At0 += yt0;
                     At1 += yt1;
                 }
+            }
+        } else if constexpr (ASIAN && SPLIT) {
+            // the lane's own scenario: weight e^{rt} of its grid; B, C, D3 (base
+            // grid) matter on the base lane only
+            if (is_fixing(L.fix_bits, j + 1)) {
+                const R *tw = reinterpret_cast<const R *>(L.step_weights) + STEP_WEIGHTS * j;
+                const R e = exp2r(y);
+                A += tw[scen == 3 ? 4 : scen == 4 ? 5 : 0] * e;
+                B += tw[1] * e;
+                C += tw[2] * e;
+                D3 += tw[3] * e;
             }
         } else if constexpr (ASIAN) {
             if (is_fixing(L.fix_bits, j + 1)) {
@@ -367,6 +399,11 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
         const R z1l = za * z1c;
         const R z2 = rhoc * za + rhobc * zb;
         const R z2m1 = z2 * z2 - R(1);
+        if constexpr (SPLIT) {
+            scaled_step<R, FT>(y, w, gs, z1l, gs.ktdt2 + gs.qdt2 * z2m1, (gs.sdt * FS) * z2);
+            fixing(j);
+            return;
+        }
         const R ab = gb.ktdt2 + gb.qdt2 * z2m1, sb = (gb.sdt * FS) * z2;
         if constexpr (SCH == 3) {
             const bool rf = L.reflect;
@@ -562,6 +599,23 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
             walk(std::true_type{});
         else
             walk(std::false_type{});
+    }
+
+    if constexpr (SPLIT) {
+        // the base lane takes the bumped scenarios' final states from its four
+        // neighbours; only it contributes to the sums
+        const int l = (int)(threadIdx.x & 63);
+        yv0 = __shfl(y, l + 1, 64);
+        yv1 = __shfl(y, l + 2, 64);
+        yt0 = __shfl(y, l + 3, 64);
+        yt1 = __shfl(y, l + 4, 64);
+        if constexpr (ASIAN) {
+            Av0 = __shfl(A, l + 1, 64);
+            Av1 = __shfl(A, l + 2, 64);
+            At0 = __shfl(A, l + 3, 64);
+            At1 = __shfl(A, l + 4, 64);
+        }
+        active = active && scen == 0;
     }
 
     // ---- payoffs and Greek samples, in FP64 ----
@@ -910,6 +964,16 @@ hipError_t launch_t(const PriceLaunch &L, hipStream_t s)
 {
     const dim3 grid(L.blocks_per_rep, L.n_reps);
     const size_t smem = RNG == 1 ? (size_t)L.bridge_depth * 2 * BLOCK * sizeof(R) : 0;
+    if constexpr (sizeof(R) == 8 && RNG == 0 && BUMPS && (AV == 0 || AV == 1) &&
+                  (SCH == 0 || SCH == 1)) {
+        if (L.split) {
+            hipLaunchKernelGGL((price_kernel<R, RNG, AV, BUMPS, SCH, true>), grid, dim3(BLOCK), 0,
+                               s, L);
+            return hipGetLastError();
+        }
+    }
+    if (L.split)
+        return hipErrorInvalidValue; // the host offers the split layout only where it exists
     hipLaunchKernelGGL((price_kernel<R, RNG, AV, BUMPS, SCH>), grid, dim3(BLOCK), smem, s, L);
     return hipGetLastError();
 }

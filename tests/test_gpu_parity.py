@@ -119,6 +119,43 @@ def test_fp64_all_types_ragged(hm, ctx, opt_type, scheme):
     check_records(d, p, opt_type, N, seed, 0, n, 0, scheme, fix, True)
 
 
+def _estimates_match(r, ref):
+    # Where a Greek's samples vanish on every path (a Gamma over a few paths
+    # all on one side of the strike) its standard error is rounding noise, so
+    # the error takes the estimate's absolute floor.
+    for k, (v, se) in ref.items():
+        assert r[k][0] == pytest.approx(v, rel=1e-10, abs=1e-12), k
+        assert r[k][1] == pytest.approx(se, rel=1e-6, abs=1e-12), k
+
+
+@pytest.mark.parametrize("opt_type", [0, 1, 2, 3])
+@pytest.mark.parametrize("scheme", [0, 1, 3, 4])
+@pytest.mark.parametrize("n", [5, 1037])
+def test_fp64_small_bump_estimates(hm, ctx, opt_type, scheme, n):
+    """Estimates of small FP64 bump launches, which the kernel lays out one
+    scenario per lane: a count below one wave's paths and a ragged count over
+    many blocks, Milstein and Euler under both fixes, daily and sparse
+    fixings."""
+    N, seed = 11, 0x5EED0000 + n
+    fix = (1, 4, 11) if opt_type >= 2 else None
+    p = PP if scheme in (1, 4) else PB
+    mode = {0: oracle.FULL_TRUNC, 1: oracle.ABSORB, 3: oracle.EULER_FULL_TRUNC,
+            4: oracle.EULER_ABSORB}[scheme]
+    r = ctx.price_greeks(p.__dict__, opt_type, n, N, seed, hm.Options(scheme=scheme, fixings=fix))
+    ref = oracle.price_greeks(p, opt_type, n, N, seed, mode, fix, threads=8)
+    _estimates_match(r, ref)
+
+
+@pytest.mark.parametrize("opt_type", [0, 3])
+@pytest.mark.parametrize("n", [12288, 12289])
+def test_fp64_bump_estimates_at_layout_limit(hm, ctx, opt_type, n):
+    """Either side of the largest count laid out one scenario per lane: both
+    layouts give the oracle's estimates."""
+    N, seed = 9, 77
+    r = ctx.price_greeks(PB.__dict__, opt_type, n, N, seed, hm.Options())
+    _estimates_match(r, oracle.price_greeks(PB, opt_type, n, N, seed, threads=8))
+
+
 @pytest.mark.parametrize("opt_type", [0, 1, 2, 3])
 def test_fp32_all_types(hm, ctx, opt_type):
     n, N, seed = 4096 + 100, 63, 7
