@@ -337,7 +337,7 @@ bool split_layout(const Request &q, const PriceLaunch &L, uint64_t count)
 {
     return q.o.precision == HESTON_FP64 && L.rng == HESTON_RNG_PHILOX && L.bumps && !L.cv &&
            (L.scheme == 0 || L.scheme == 1) && q.type <= HESTON_ASIAN_PUT &&
-           count <= SPLIT_MAX_PATHS;
+           count <= (q.type >= HESTON_ASIAN_CALL ? SPLIT_MAX_PATHS_ASIAN : SPLIT_MAX_PATHS_EURO);
 }
 // Paths per block of the launch.
 uint64_t paths_per_block(const PriceLaunch &L)

@@ -34,9 +34,12 @@ constexpr uint32_t QE_COUNTER_TAG = 4u;
 // Largest per-block Sobol table (ceil(M/64) x 2N words) built for a launch;
 // above it the kernel combines the high direction numbers itself.
 // Scenario-split layout of small FP64 bump launches (price_kernel SPLIT):
-// paths per wave, and the largest launch it is used for (about one wave per SIMD).
+// paths per wave, and the largest launches it is used for, measured crossovers
+// with the fused layout at 100 steps: about three waves per SIMD for European
+// payoffs, eight for arithmetic Asians (whose fixings lengthen the fused step).
 constexpr uint32_t SPLIT_PATHS_PER_WAVE = 12;
-constexpr uint64_t SPLIT_MAX_PATHS = 12288;
+constexpr uint64_t SPLIT_MAX_PATHS_EURO = 36864;
+constexpr uint64_t SPLIT_MAX_PATHS_ASIAN = 98304;
 constexpr uint64_t SOBOL_HI_MAX_BYTES = 256ull << 20;
 // Fixing weights per step j (fixing time t = (j+1) dt): e^{rt}, t e^{rt},
 // t^2 e^{rt}, t^3 e^{rt} on the base grid, e^{rt} on the T + hT and T - hT grids.

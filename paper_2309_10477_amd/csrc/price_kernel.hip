@@ -279,9 +279,10 @@ __device__ __forceinline__ bool any_lane(bool c)
 // (base, v0+, v0-, T+, T-; lanes 60-63 idle) -- with that scenario's grid,
 // initial variance and fixing weight, and the base lane gathers the other four
 // final states before the payoffs.  Every scenario takes the same operations
-// as in the fused layout, so the per-path values are the same; a wave does
-// about half the work per step of the fused layout's, which pays only while
-// the launch has at most about one wave per SIMD.
+// as in the fused layout, so the per-path values are the same.  With the
+// path's draws shared by its five lanes a wave's step is about a fifth of the
+// fused layout's for a fifth of its paths: shorter waves, slightly more
+// instructions per path, which pays while the launch has few waves per SIMD.
 template <class R, int RNG, int AV, bool BUMPS, int SCH, bool SPLIT = false>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void price_kernel(
@@ -479,17 +480,53 @@ __attribute__((amdgpu_waves_per_eu(SCH == 2 && sizeof(R) == 4 ? 6 : 1))) void pr
             rhoc = (R)(L.rho * NS);
             rhobc = (R)(L.rho_bar * NS);
         }
-        uint32_t j = 0;
-        for (; j + 1 < N; j += 2) {
-            R za0, zb0, za1, zb1;
-            philox_normals<R, SCALED>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
-            step(j, za0, zb0);
-            step(j + 1, za1, zb1);
-        }
-        if (j < N) {
-            R za0, zb0, za1, zb1;
-            philox_normals<R, SCALED>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
-            step(j, za0, zb0);
+        if constexpr (SPLIT) {
+            // The five lanes of a path share its normals.  Over a group of
+            // ten steps the lane of scenario s draws the Philox block of steps
+            // j0 + 2s and j0 + 2s + 1, and each lane reads every step's pair
+            // from the lane that drew it, so a lane computes a fifth of the
+            // path's draws.  The next group is drawn while the current one is
+            // stepped.  (Lanes 60-63 read within their group or lane 63.)
+            constexpr uint32_t G = 10;
+            const int src0 = (int)(threadIdx.x & 63u) - (int)scen;
+            R a0, b0, a1, b1, za[G], zb[G];
+            philox_normals<R, false>(2 * scen, plo, phi, k0, k1, a0, b0, a1, b1);
+            auto gather = [&]() {
+#pragma unroll
+                for (uint32_t k = 0; k < G; ++k) {
+                    const int src = min(src0 + (int)(k >> 1), 63);
+                    za[k] = __shfl((k & 1) ? a1 : a0, src, 64);
+                    zb[k] = __shfl((k & 1) ? b1 : b0, src, 64);
+                }
+            };
+            uint32_t j0 = 0;
+            for (; j0 + G <= N; j0 += G) {
+                gather();
+                philox_normals<R, false>(j0 + G + 2 * scen, plo, phi, k0, k1, a0, b0, a1, b1);
+#pragma unroll
+                for (uint32_t k = 0; k < G; ++k)
+                    step(j0 + k, za[k], zb[k]);
+            }
+            if (j0 < N) {
+                gather();
+#pragma unroll
+                for (uint32_t k = 0; k < G; ++k)
+                    if (j0 + k < N)
+                        step(j0 + k, za[k], zb[k]);
+            }
+        } else {
+            uint32_t j = 0;
+            for (; j + 1 < N; j += 2) {
+                R za0, zb0, za1, zb1;
+                philox_normals<R, SCALED>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
+                step(j, za0, zb0);
+                step(j + 1, za1, zb1);
+            }
+            if (j < N) {
+                R za0, zb0, za1, zb1;
+                philox_normals<R, SCALED>(j, plo, phi, k0, k1, za0, zb0, za1, zb1);
+                step(j, za0, zb0);
+            }
         }
     } else {
         // Sobol point i of replicate `rep`, Brownian bridge walked in time order

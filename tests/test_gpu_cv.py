@@ -8,7 +8,9 @@ parity tests (1e-12 FP64, 1e-5 FP32 relative, floor S0).  Estimates: the
 library's control mean (computed on the device by Gauss-Legendre panels)
 against the oracle's transform price (adaptive quadrature) to 1e-9 relative,
 and beta, the estimate and its error against oracle.control_variate on the
-oracle's own paths.
+oracle's own paths (FP64); in FP32, against oracle.control_variate on the
+kernel's dumped payoffs, and the gap to the oracle's estimate within the bound
+that the per-path payoff bar implies.
 """
 import math
 
@@ -51,6 +53,27 @@ def close(name, g, o, tol, floor):
                              f"gpu {g[i]!r} oracle {o[i]!r} rel {err[i]:.3e}")
 
 
+def fp32_estimate(r, d, a, g, mu, est_o, beta_o, R=None):
+    """FP32 estimate checks.  The library's combination of its own FP64 sums
+    equals the oracle's formula applied to the payoffs the kernel dumps; the
+    gap from there to the oracle's estimate follows exactly from the per-path
+    payoff errors: est_d - est_o = mean(a_d - a) - beta_d mean(g_d - g)
+    - (beta_d - beta_o)(mean(g) - mu), each payoff error at most 1e-5 of
+    max(S0, payoff) by the per-path check."""
+    ad, gd = d[:, 3], d[:, 15]
+    if R is None:
+        est_d, se_d, beta_d = oracle.control_variate(ad, gd, mu)
+    else:
+        est_d, se_d, beta_d = oracle.control_variate_reps(ad, gd, mu, R)
+    assert r["cv_beta"] == pytest.approx(beta_d, rel=1e-9)
+    assert r["cv_price"][0] == pytest.approx(est_d, rel=1e-9)
+    assert r["cv_price"][1] == pytest.approx(se_d, rel=1e-6)
+    assert beta_d == pytest.approx(beta_o, rel=1e-3)
+    scale = TOL[1] * max(PB.S0, np.abs(a).max(), np.abs(g).max())
+    bar = scale * (1 + abs(beta_d)) + abs(beta_d - beta_o) * abs(g.mean() - mu)
+    assert abs(est_d - est_o) <= bar, (est_d, est_o, bar)
+
+
 def oracle_pays(p, opt, N, seed, n, mode, fix, za=None, zb=None):
     if mode == oracle.QE:
         a = oracle.simulate_qe(p, opt, N, seed, 0, n, fix, threads=8)[0][:, 3]
@@ -81,10 +104,7 @@ def test_dumped_payoffs_and_estimate(hm, ctx, prec, opt, fix):
         assert r["cv_price"][0] == pytest.approx(est, rel=1e-9)
         assert r["cv_price"][1] == pytest.approx(se, rel=1e-6)
     else:
-        # the FP32 payoffs carry 1e-5 of S0 per path, beta takes their
-        # correlation, and the estimate moves by at most that through beta
-        assert r["cv_beta"] == pytest.approx(beta, rel=1e-3)
-        assert r["cv_price"][0] == pytest.approx(est, abs=2e-4 * PB.S0)
+        fp32_estimate(r, d, a, g, mu, est, beta)
     plain = oracle.mean_se(a)
     assert r["price"][0] == pytest.approx(plain[0], rel=1e-9 if prec == 0 else 1e-5)
 
@@ -135,7 +155,7 @@ def test_sobol_replicates(hm, ctx, prec):
         assert r["cv_price"][0] == pytest.approx(est, rel=1e-9)
         assert r["cv_price"][1] == pytest.approx(se, rel=1e-6)
     else:
-        assert r["cv_price"][0] == pytest.approx(est, abs=2e-4 * PB.S0)
+        fp32_estimate(r, d, a, g, mu, est, beta, R)
 
 
 @pytest.mark.parametrize("p", [PB.replace(T=0.1, sigma=1.0, kappa=0.5),

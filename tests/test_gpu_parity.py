@@ -146,11 +146,11 @@ def test_fp64_small_bump_estimates(hm, ctx, opt_type, scheme, n):
     _estimates_match(r, ref)
 
 
-@pytest.mark.parametrize("opt_type", [0, 3])
-@pytest.mark.parametrize("n", [12288, 12289])
+@pytest.mark.parametrize("opt_type,n", [(0, 36864), (0, 36865), (3, 98304), (3, 98305)])
 def test_fp64_bump_estimates_at_layout_limit(hm, ctx, opt_type, n):
-    """Either side of the largest count laid out one scenario per lane: both
-    layouts give the oracle's estimates."""
+    """Either side of the largest count laid out one scenario per lane
+    (36864 European, 98304 Asian paths): both layouts give the oracle's
+    estimates."""
     N, seed = 9, 77
     r = ctx.price_greeks(PB.__dict__, opt_type, n, N, seed, hm.Options())
     _estimates_match(r, oracle.price_greeks(PB, opt_type, n, N, seed, threads=8))
