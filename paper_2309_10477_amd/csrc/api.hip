@@ -488,8 +488,10 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
         if (c->host_sums)
             (void)hipHostFree(c->host_sums);
         c->host_sums = nullptr;
+        c->host_sums_dev = nullptr;
         c->host_sums_bytes = 0;
         HIP_TRY(hipHostMalloc((void **)&c->host_sums, (size_t)L.n_reps * W * 8));
+        HIP_TRY(hipHostGetDevicePointer((void **)&c->host_sums_dev, c->host_sums, 0));
         c->host_sums_bytes = (size_t)L.n_reps * W * 8;
     }
     return HESTON_OK;
@@ -1083,15 +1085,15 @@ static heston_status price_greeks_impl(heston_ctx *c, const heston_params *param
     HIP_TRY(hipEventRecord(c->ev0, c->stream));
     HIP_TRY(launch_paths(L, c->stream));
     HIP_TRY(hipEventRecord(c->ev1, c->stream));
-    HIP_TRY(launch_reduce(L, (double *)c->rep_sums.ptr, c->stream));
+    // the last reduction level writes the sums into the pinned host buffer
+    // (no copy launch); the host reads them after the stream synchronises
+    HIP_TRY(launch_reduce(L, c->host_sums_dev, c->stream));
     double geo_out[2] = {0, 0};
     if (L.cv) {
         HIP_TRY(hipStreamWaitEvent(c->stream, c->join, 0));
         HIP_TRY(hipMemcpyAsync(geo_out, (double *)c->geo_buf.ptr + GEO_OUT, sizeof(geo_out),
                                hipMemcpyDeviceToHost, c->stream));
     }
-    HIP_TRY(hipMemcpyAsync(c->host_sums, c->rep_sums.ptr, (size_t)L.n_reps * L.acc_width() * 8,
-                           hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (L.cv && !(std::isfinite(geo_out[0]) && std::isfinite(geo_out[1]))) {
         // the transform had not decayed by the end of the fixed range: search

@@ -27,7 +27,9 @@ struct heston_ctx {
     DevBuf exact_scratch;                    // exact sampler: Re Phi per lane
     DevBuf reduce_tmp;                       // first-level sums of long reductions
     DevBuf batch_opts, batch_items, batch_partials, batch_sums, batch_counter, batch_scratch;
-    double *host_sums = nullptr; // pinned
+    double *host_sums = nullptr;     // pinned
+    double *host_sums_dev = nullptr; // its device address: the estimate
+                                     // reduction writes its sums straight there
     size_t host_sums_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // side stream (default priority, created on first use) on which the
