@@ -46,6 +46,7 @@ heston_status reserve(heston_ctx *c, DevBuf &b, size_t bytes)
     }
     HIP_TRY(hipMalloc(&b.ptr, bytes));
     b.bytes = bytes;
+    b.gen = ++c->alloc_gen;
     c->in_use += bytes;
     return HESTON_OK;
 }
@@ -95,12 +96,6 @@ StepCoef step_coef(const heston_params &p, double T, uint32_t N)
 // every pending midpoint between j and the smallest end-point already known,
 // B_m = a B_j + b B_top + c z_node with a = (r-m)/(r-l), b = (m-l)/(r-l),
 // c = sqrt((m-l)(r-m)/(r-l)), pushing each on a stack; then it pops B_{j+1}.
-struct BridgePlan {
-    std::vector<int32_t> start; // N+1
-    std::vector<BridgeOp> ops;  // N-1
-    int depth = 1;
-};
-
 bool bridge_program(uint32_t N, BridgePlan &plan)
 {
     std::vector<int32_t> node_of(N + 1, -1), left(N + 1, -1), right(N + 1, -1);
@@ -375,18 +370,37 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
         M = q.n_paths / R;
         L.rep0 = (uint32_t)(first / M);
         L.n_reps = (uint32_t)((first + count - 1) / M) - L.rep0 + 1;
-        BridgePlan bp;
-        if (!bridge_program(q.n_steps, bp))
-            return fail(HESTON_DEVICE_ERROR, "internal: Brownian bridge walk inconsistent");
+        // The tables that do not depend on the seed (direction numbers,
+        // bridge walk, the block-aligned walk's position tables and per-block
+        // table) are rebuilt only when the step count or the direction numbers
+        // change, or when their buffer has been reallocated; the seeded shifts
+        // are drawn on every call.
+        SobolTables &T = c->sobol;
+        const uint32_t N = q.n_steps;
+        const size_t dir_words = (size_t)dims * 32;
+        if (!(T.n_steps == N && T.dirs.size() == dir_words &&
+              std::memcmp(T.dirs.data(), o.sobol_directions, dir_words * 4) == 0)) {
+            // the host tables are replaced: let copies still reading them finish
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            T = SobolTables{};
+            if (!bridge_program(N, T.bp))
+                return fail(HESTON_DEVICE_ERROR, "internal: Brownian bridge walk inconsistent");
+            T.n_steps = N;
+            T.dirs.assign(o.sobol_directions, o.sobol_directions + dir_words);
+        }
+        const BridgePlan &bp = T.bp;
         heston_status st;
-        if ((st = reserve(c, c->sobol_dirs, (size_t)dims * 32 * 4)) != HESTON_OK ||
+        if ((st = reserve(c, c->sobol_dirs, dir_words * 4)) != HESTON_OK ||
             (st = reserve(c, c->sobol_shift, (size_t)dims * R * 4)) != HESTON_OK ||
-            (st = reserve(c, c->bridge_start, (q.n_steps + 1) * 4)) != HESTON_OK ||
+            (st = reserve(c, c->bridge_start, (N + 1) * 4)) != HESTON_OK ||
             (st = reserve(c, c->bridge_ops, std::max<size_t>(1, bp.ops.size()) * sizeof(BridgeOp))) !=
                 HESTON_OK)
             return st;
-        HIP_TRY(hipMemcpyAsync(c->sobol_dirs.ptr, o.sobol_directions, (size_t)dims * 32 * 4,
-                               hipMemcpyHostToDevice, c->stream));
+        if (T.dirs_gen != c->sobol_dirs.gen) {
+            HIP_TRY(hipMemcpyAsync(c->sobol_dirs.ptr, T.dirs.data(), dir_words * 4,
+                                   hipMemcpyHostToDevice, c->stream));
+            T.dirs_gen = c->sobol_dirs.gen;
+        }
         // Blocks of 64 consecutive points share their Gray-code bits >= 6; when the
         // launch's waves are block-aligned, the XOR of those bits' direction numbers
         // is tabulated once per block and dimension; the XOR of the direction
@@ -398,15 +412,12 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
         // device memory) the kernel combines the direction numbers itself.
         L.sobol_hi = nullptr;
         L.sobol_low = nullptr;
-        const uint32_t N = q.n_steps;
         const uint64_t n_blk = (M + 63) / 64, hi_bytes = n_blk * dims * 4;
         // the low-bit table [N+1][64][2] follows the [N][12] direction numbers it is built from
         const uint64_t low_bytes = (uint64_t)N * 48 + ((uint64_t)N + 1) * 512;
         const uint64_t extra = hi_bytes + (uint64_t)N * 4 + low_bytes;
         const uint64_t held = c->sobol_hi.bytes + c->sobol_perm.bytes + c->sobol_low.bytes;
         const bool fits = !c->budget || c->in_use - held + extra + 3 * 4096 <= c->budget;
-        std::vector<int32_t> node_of_pos;
-        std::vector<uint32_t> dir12;
         bool fast = M % 64 == 0 && (first % M) % 64 == 0 && hi_bytes <= SOBOL_HI_MAX_BYTES && fits;
         if (fast) {
             if ((st = reserve(c, c->sobol_hi, hi_bytes)) == HESTON_OK &&
@@ -420,40 +431,56 @@ heston_status plan(heston_ctx *c, const Request &q, uint64_t first, uint64_t cou
             }
         }
         if (fast) {
-            node_of_pos.resize(N);
-            node_of_pos[0] = 0;
-            for (size_t k = 0; k < bp.ops.size(); ++k)
-                node_of_pos[k + 1] = bp.ops[k].node;
-            dir12.resize((size_t)N * 12);
-            for (uint32_t pos = 0; pos < N; ++pos)
-                for (uint32_t mm = 0; mm < 2; ++mm)
-                    for (uint32_t b = 0; b < 6; ++b)
-                        dir12[pos * 12 + mm * 6 + b] =
-                            o.sobol_directions[(size_t)(2 * node_of_pos[pos] + mm) * 32 + b];
-            HIP_TRY(hipMemcpyAsync(c->sobol_perm.ptr, node_of_pos.data(), (size_t)N * 4,
-                                   hipMemcpyHostToDevice, c->stream));
+            if (T.node_of_pos.empty()) {
+                T.node_of_pos.resize(N);
+                T.node_of_pos[0] = 0;
+                for (size_t k = 0; k < bp.ops.size(); ++k)
+                    T.node_of_pos[k + 1] = bp.ops[k].node;
+                T.dir12.resize((size_t)N * 12);
+                for (uint32_t pos = 0; pos < N; ++pos)
+                    for (uint32_t mm = 0; mm < 2; ++mm)
+                        for (uint32_t b = 0; b < 6; ++b)
+                            T.dir12[pos * 12 + mm * 6 + b] =
+                                T.dirs[(size_t)(2 * T.node_of_pos[pos] + mm) * 32 + b];
+            }
+            if (T.perm_gen != c->sobol_perm.gen) {
+                HIP_TRY(hipMemcpyAsync(c->sobol_perm.ptr, T.node_of_pos.data(), (size_t)N * 4,
+                                       hipMemcpyHostToDevice, c->stream));
+                T.perm_gen = c->sobol_perm.gen;
+                T.hi_gen = 0; // the per-block table is ordered by this permutation
+            }
             uint32_t *d12 = (uint32_t *)c->sobol_low.ptr, *low = d12 + (size_t)N * 12;
-            HIP_TRY(hipMemcpyAsync(d12, dir12.data(), (size_t)N * 48, hipMemcpyHostToDevice,
-                                   c->stream));
-            HIP_TRY(launch_sobol_low(d12, N, low, c->stream));
+            if (T.low_gen != c->sobol_low.gen) {
+                HIP_TRY(hipMemcpyAsync(d12, T.dir12.data(), (size_t)N * 48, hipMemcpyHostToDevice,
+                                       c->stream));
+                HIP_TRY(launch_sobol_low(d12, N, low, c->stream));
+                T.low_gen = c->sobol_low.gen;
+            }
             const int32_t *perm = (const int32_t *)c->sobol_perm.ptr;
             HIP_TRY(launch_sobol_shifts(q.seed, perm, dims, R, (uint32_t *)c->sobol_shift.ptr,
                                         c->stream));
-            HIP_TRY(launch_sobol_hi((const uint32_t *)c->sobol_dirs.ptr, perm, dims, (uint32_t)n_blk,
-                                    (uint32_t *)c->sobol_hi.ptr, c->stream));
+            if (T.hi_gen != c->sobol_hi.gen || T.hi_blocks != n_blk) {
+                HIP_TRY(launch_sobol_hi((const uint32_t *)c->sobol_dirs.ptr, perm, dims,
+                                        (uint32_t)n_blk, (uint32_t *)c->sobol_hi.ptr, c->stream));
+                T.hi_gen = c->sobol_hi.gen;
+                T.hi_blocks = n_blk;
+            }
             L.sobol_hi = (const uint32_t *)c->sobol_hi.ptr;
             L.sobol_low = low;
         } else {
             HIP_TRY(launch_sobol_shifts(q.seed, nullptr, dims, R, (uint32_t *)c->sobol_shift.ptr,
                                         c->stream));
         }
-        HIP_TRY(hipMemcpyAsync(c->bridge_start.ptr, bp.start.data(), (q.n_steps + 1) * 4,
-                               hipMemcpyHostToDevice, c->stream));
-        if (!bp.ops.empty())
+        if (T.start_gen != c->bridge_start.gen) {
+            HIP_TRY(hipMemcpyAsync(c->bridge_start.ptr, bp.start.data(), (N + 1) * 4,
+                                   hipMemcpyHostToDevice, c->stream));
+            T.start_gen = c->bridge_start.gen;
+        }
+        if (!bp.ops.empty() && T.ops_gen != c->bridge_ops.gen) {
             HIP_TRY(hipMemcpyAsync(c->bridge_ops.ptr, bp.ops.data(), bp.ops.size() * sizeof(BridgeOp),
                                    hipMemcpyHostToDevice, c->stream));
-        // The host vectors die at return; finish the copies first.
-        HIP_TRY(hipStreamSynchronize(c->stream));
+            T.ops_gen = c->bridge_ops.gen;
+        }
         L.sobol_dirs = (const uint32_t *)c->sobol_dirs.ptr;
         L.sobol_shift = (const uint32_t *)c->sobol_shift.ptr;
         L.bridge_start = (const int32_t *)c->bridge_start.ptr;

@@ -481,3 +481,47 @@ def test_sobol_directions_wider_than_30_bits_rejected(hm, ctx):
     st = hm.lib().heston_price_greeks_ex(ctx.handle, ctypes.byref(cp), 0, 512, N, 1,
                                          ctypes.byref(o.c), ctypes.byref(res))
     assert st == 0
+
+
+def _sobol_estimates(hm, ctx, dirs, N, n, seed, R=4):
+    """heston_price_greeks_ex with the Sobol + bridge generator on the given
+    direction-number table (FP64 Asian put, fused bumps)."""
+    import ctypes
+    o = hm._OptsHolder(hm.Options(rng=hm.SOBOL_BRIDGE, qmc_replicates=R), N)
+    o.dirs = dirs
+    o.c.sobol_directions = dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    o.c.sobol_dims = dirs.shape[0]
+    res = hm.CResult()
+    cp = hm._cparams(PB.__dict__)
+    hm.check(hm.lib().heston_price_greeks_ex(ctx.handle, ctypes.byref(cp), hm.ASIAN_PUT, n, N,
+                                             seed, ctypes.byref(o.c), ctypes.byref(res)))
+    r = hm._result_dict(res)
+    return {k: r[k] for k in hm.EST_NAMES}
+
+
+def test_sobol_tables_kept_between_calls(hm, ctx):
+    """A context keeps the seed-independent quasi-random tables from one call to
+    the next.  A sequence of calls on one context that changes the step count,
+    the points per replicate (64-point aligned or not, a larger per-block
+    table), the direction numbers (another table, or the same array changed in
+    place) and the seed gives, call by call, bitwise the results of a fresh
+    context."""
+    base12 = hm.sobol_directions(24)
+    base20 = hm.sobol_directions(40)
+    other12 = base12.copy()
+    other12[1:, :30] ^= np.uint32(0x15555555) >> np.arange(30, dtype=np.uint32)
+    inplace = base12.copy()
+    seq = [(base12, 12, 2048, 1), (base20, 20, 2048, 2), (base12, 12, 2048, 3),
+           (base12, 12, 2000, 4), (other12, 12, 2048, 5), (base12, 12, 8192, 6),
+           (base12, 12, 2048, 1), (inplace, 12, 2048, 7), ("mutate", 12, 2048, 7)]
+    for dirs, N, n, seed in seq:
+        if isinstance(dirs, str):  # same array, new contents
+            inplace[3:, 2:30] ^= np.uint32(0x2AAAAAAA) >> np.arange(2, 30, dtype=np.uint32)
+            dirs = inplace
+        got = _sobol_estimates(hm, ctx, dirs, N, n, seed)
+        fresh = hm.Context(0)
+        try:
+            want = _sobol_estimates(hm, fresh, dirs, N, n, seed)
+        finally:
+            fresh.close()
+        assert got == want, (N, n, seed)
