@@ -824,6 +824,8 @@ heston_status heston_ctx_destroy(heston_ctx *c)
             (void)hipFree(b->ptr);
     if (c->host_sums)
         (void)hipHostFree(c->host_sums);
+    if (c->host_geo)
+        (void)hipHostFree(c->host_geo);
     (void)hipEventDestroy(c->ev0);
     (void)hipEventDestroy(c->ev1);
     if (c->side) {
@@ -919,6 +921,8 @@ static heston_status geo_control_setup(heston_ctx *c, const Request &q, GeoContr
     if ((st = reserve(c, c->geo_buf, GEO_BUF_DOUBLES * 8)) != HESTON_OK ||
         (st = reserve(c, c->geo_partials, (size_t)geo_node_blocks() * 8)) != HESTON_OK)
         return st;
+    if (!c->host_geo)
+        HIP_TRY(hipHostMalloc((void **)&c->host_geo, 2 * sizeof(double)));
     if (!c->side) {
         HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
@@ -1115,10 +1119,10 @@ static heston_status price_greeks_impl(heston_ctx *c, const heston_params *param
     // the last reduction level writes the sums into the pinned host buffer
     // (no copy launch); the host reads them after the stream synchronises
     HIP_TRY(launch_reduce(L, c->host_sums_dev, c->stream));
-    double geo_out[2] = {0, 0};
+    double *geo_out = c->host_geo; // pinned (set up with the control)
     if (L.cv) {
         HIP_TRY(hipStreamWaitEvent(c->stream, c->join, 0));
-        HIP_TRY(hipMemcpyAsync(geo_out, (double *)c->geo_buf.ptr + GEO_OUT, sizeof(geo_out),
+        HIP_TRY(hipMemcpyAsync(geo_out, (double *)c->geo_buf.ptr + GEO_OUT, 2 * sizeof(double),
                                hipMemcpyDeviceToHost, c->stream));
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1126,7 +1130,7 @@ static heston_status price_greeks_impl(heston_ctx *c, const heston_params *param
         // the transform had not decayed by the end of the fixed range: search
         HIP_TRY(launch_geo_price_search(gc, (double *)c->geo_partials.ptr,
                                         (double *)c->geo_buf.ptr, c->stream));
-        HIP_TRY(hipMemcpyAsync(geo_out, (double *)c->geo_buf.ptr + GEO_OUT, sizeof(geo_out),
+        HIP_TRY(hipMemcpyAsync(geo_out, (double *)c->geo_buf.ptr + GEO_OUT, 2 * sizeof(double),
                                hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
     }

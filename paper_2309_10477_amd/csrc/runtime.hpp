@@ -60,6 +60,7 @@ struct heston_ctx {
     double *host_sums_dev = nullptr; // its device address: the estimate
                                      // reduction writes its sums straight there
     size_t host_sums_bytes = 0;
+    double *host_geo = nullptr; // pinned: the geometric control's call and put prices
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // side stream (default priority, created on first use) on which the
     // geometric control's price runs beside the path kernel
