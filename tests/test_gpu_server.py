@@ -70,7 +70,10 @@ def test_alone_and_in_the_mix(hm, ctx, want):
     # latency: submit to completion; device time: the launches that carried its items
     lat = np.array([r["latency_ms"] for r in mix])
     assert (lat > 0).all() and stats["p50_ms"] == pytest.approx(np.percentile(lat, 50), rel=0.05)
-    assert all(0 < r["device_ms"] <= r["latency_ms"] for r in mix)
+    # device time sums the durations of the launches that carried the request's
+    # items; at most three launches (the engine's launch slots) are in flight at
+    # once, so the sum is at most three times the request's wall latency
+    assert all(0 < r["device_ms"] <= 3 * r["latency_ms"] for r in mix)
     for i in (0, 5, 17):
         alone, _ = serve(hm, ctx, [reqs[i]], precision=hm.FP32)
         for k in ("price", "pw_delta", "pw_rho", "adj", "n_paths"):
