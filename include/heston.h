@@ -204,7 +204,10 @@ typedef struct heston_opts {
     uint32_t n_fixings;
     double bump_S0_rel; /* default 0.01   (h = bump_S0_rel * S0)      */
     double bump_v0_rel; /* default 0.01   (h = bump_v0_rel * v0)      */
-    double bump_r_abs;  /* default 1e-4                               */
+    double bump_r_abs;  /* default 1e-4; with fused bumps of an arithmetic
+                           Asian bump_r_abs * T <= 1e-3 (FP64) or 3e-3 (FP32):
+                           its r-bumped averages come from a Taylor series in
+                           the bump (else HESTON_INVALID_ARGUMENT)          */
     double bump_T_abs;  /* default 1/365; n_steps and the fixing step
                            indices stay fixed, so dt is rescaled      */
     int32_t control_variate; /* HESTON_CONTROL_NONE (default) or HESTON_CONTROL_GEOMETRIC */

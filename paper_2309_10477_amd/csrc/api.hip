@@ -227,6 +227,16 @@ heston_status check_request(const Request &q)
             return fail(HESTON_INVALID_ARGUMENT, "relative v0 bump needs v0 > 0");
         if (!(o.bump_S0_rel < 1) || !(o.bump_v0_rel < 1) || !(o.bump_T_abs < q.p.T))
             return fail(HESTON_INVALID_ARGUMENT, "bumps must keep S0, v0 and T positive");
+        // The fused r bump of an arithmetic Asian sums e^{+-h t_i} over the
+        // fixings by its Taylor series in h (through h^3 in FP64, h^2 in
+        // FP32): h T is kept where the truncation stays below the parity bar
+        // of the precision, (h T)^4 / 24 <= 4.2e-14 and (h T)^3 / 6 <= 4.5e-9.
+        if ((o.greeks & HESTON_GREEKS_BUMP_FUSED) &&
+            (q.type == HESTON_ASIAN_CALL || q.type == HESTON_ASIAN_PUT) &&
+            !(o.bump_r_abs * q.p.T <= (o.precision == HESTON_FP64 ? 1e-3 : 3e-3)))
+            return fail(HESTON_INVALID_ARGUMENT,
+                        "fused r bump of an arithmetic Asian: bump_r_abs * T must be at most "
+                        "1e-3 (FP64) or 3e-3 (FP32); use a smaller bump or plain bumps");
     }
     if (o.reserved != 0)
         return fail(HESTON_INVALID_ARGUMENT, "opts->reserved must be 0");

@@ -32,7 +32,6 @@ def test_every_declared_function_is_exported(L):
 
 def test_host_only_calls(L):
     import paper_2309_10477_amd as hm
-    import paper_2309_10477_amd as hm
     assert L.heston_abi_version() == hm.ABI_VERSION
     assert L.heston_status_str(-1) == b"invalid argument"
     o = hm.COpts()
@@ -41,6 +40,24 @@ def test_host_only_calls(L):
     assert (o.precision, o.rng, o.scheme, o.greeks) == (0, 0, 0, 3)
     assert o.bump_S0_rel == 0.01 and o.bump_r_abs == 1e-4 and o.bump_T_abs == 1 / 365
     assert L.heston_default_opts(None) == -1
+
+
+def test_fused_r_bump_range_checked_on_the_host(L):
+    """A fused r bump of an arithmetic Asian takes its bumped averages from a
+    Taylor series in the bump; outside the series' range (bump_r_abs * T above
+    1e-3 in FP64, 3e-3 in FP32) the call is rejected while checking its
+    arguments, before any device work."""
+    import paper_2309_10477_amd as hm
+    from workloads import BASE
+    res = hm.CResult()
+    for prec, h, T, typ in ((hm.FP64, 2e-3, 1.0, hm.ASIAN_CALL), (hm.FP64, 1e-4, 20.0, hm.ASIAN_PUT),
+                            (hm.FP32, 4e-3, 1.0, hm.ASIAN_CALL)):
+        o = hm._OptsHolder(hm.Options(precision=prec, bump_r_abs=h), 8)
+        cp = hm._cparams(dict(BASE, T=T))
+        st = L.heston_price_greeks_noalloc(ctypes.byref(cp), typ, 1000, 8, 1, ctypes.byref(o.c),
+                                           None, ctypes.byref(res))
+        assert st == -1, (prec, h, T)
+        assert b"bump_r_abs" in L.heston_last_error()
 
 
 def test_struct_layout_matches_header():

@@ -146,6 +146,27 @@ def test_fp64_small_bump_estimates(hm, ctx, opt_type, scheme, n):
     _estimates_match(r, ref)
 
 
+@pytest.mark.parametrize("prec,h", [(0, 1e-3), (1, 3e-3)])
+def test_fused_r_bump_at_its_largest(hm, ctx, prec, h):
+    """The largest r bump the fused arithmetic-Asian kernel takes (bump_r_abs T
+    = 1e-3 in FP64, 3e-3 in FP32), where its Taylor series of e^{+-h t} over
+    the fixings is least accurate: per-path r-bumped payoffs against the
+    oracle's, which bumps r exactly, and in FP64 the estimates."""
+    n, N, seed = 1037, 12, 99
+    opts = hm.Options(precision=prec, bump_r_abs=h)
+    d = dump(hm, ctx, PB, hm.ASIAN_CALL, n, N, seed, 0, n, opts)
+    bumps = oracle.Bumps(r_abs=h)
+    pay, _ = oracle.scenario_payoffs(PB, oracle.ASIAN_CALL, N, seed, n, 0, oracle.FULL_TRUNC,
+                                     None, bumps, threads=8)
+    for k, sc in enumerate(oracle.SCENARIOS[1:]):
+        if sc in ("r+", "r-"):
+            compare("pay_" + sc, d[:, 6 + k], pay[sc], TOL[prec], PB.S0)
+    if prec == 0:
+        r = ctx.price_greeks(PB.__dict__, hm.ASIAN_CALL, n, N, seed, opts)
+        _estimates_match(r, oracle.price_greeks(PB, oracle.ASIAN_CALL, n, N, seed,
+                                                bumps=bumps, threads=8))
+
+
 @pytest.mark.parametrize("opt_type,n", [(0, 36864), (0, 36865), (3, 98304), (3, 98305)])
 def test_fp64_bump_estimates_at_layout_limit(hm, ctx, opt_type, n):
     """Either side of the largest count laid out one scenario per lane
